@@ -1,0 +1,294 @@
+/*
+ * oracle.c -- plain CPU FP64 reference for the reduction of a dense matrix to
+ * compact band form (Rodriguez-Sanchez, Catalan, Herrero, Quintana-Orti,
+ * Tomas: look-ahead in the two-sided reduction to compact band forms).
+ *
+ * TEST INFRASTRUCTURE ONLY.  It exists to check the HIP implementation; the
+ * product library never links, loads or calls it, and the two share no
+ * source.  Build: gcc -O2 -ffp-contract=off -fopenmp (no fast-math), so every
+ * product and sum is rounded once, in IEEE double, in program order.
+ *
+ * What it computes (see oracle.h for the storage contract):
+ *   - sy2sb: Sec. 2.1.  Each reflector H = I - tau v v^T annihilates column c
+ *     below row c+w; the similarity H A2 H of the trailing block uses the
+ *     symmetric rank-2 form of eqs. updateA2symm..updateA2syr2k taken at block
+ *     size 1 (p = tau A2 v, K = tau p^T v / 2, q = p - K v,
+ *     A2 -= v q^T + q v^T); the in-band columns between the reflector column
+ *     and the trailing block only see H from the left (eq. updateA1).
+ *   - ge2gb: Sec. 3.1, eqs. updateB..updateD at block size 1: a left
+ *     reflector annihilates column c below the diagonal and is applied from
+ *     the left to the columns right of it; a right reflector annihilates
+ *     row c right of column c+w and is applied from the right to the rows
+ *     below it.
+ *   - The reflector itself is the textbook Householder vector (Golub and Van
+ *     Loan, the reference the paper cites for the WY machinery): with
+ *     alpha = x0, sigma = ||x[1:]||, beta = -sign(alpha) hypot(alpha, sigma),
+ *     tau = (beta - alpha) / beta, v = [1; x[1:] / (alpha - beta)], and
+ *     tau = 0, beta = alpha when sigma = 0.  sign(+-0) = +1.
+ *
+ * Parallelism: OpenMP over independent columns (or row chunks) only; every
+ * sum is accumulated by one thread in a fixed order, so results do not depend
+ * on the thread count.
+ *
+ * ORACLE_MUTANT (compile-time, default 0) plants one deliberate mistake; the
+ * test-suite builds such variants to show that its pins catch them.  A normal
+ * build never defines it.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#ifndef ORACLE_MUTANT
+#define ORACLE_MUTANT 0
+#endif
+
+int oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* Euclidean norm of x[0..L-1] (stride inc), scaled by max |x_i| so that the
+ * squares neither overflow nor underflow. */
+static double norm2_scaled(int64_t L, const double *x, int64_t inc) {
+  double m = 0.0;
+  for (int64_t i = 0; i < L; ++i) {
+    double a = fabs(x[i * inc]);
+    if (a > m) m = a;
+  }
+  if (m == 0.0) return 0.0;
+  double s = 0.0;
+  for (int64_t i = 0; i < L; ++i) {
+    double t = x[i * inc] / m;
+    s += t * t;
+  }
+  return m * sqrt(s);
+}
+
+double oracle_house(int64_t L, double *x, int64_t inc, double *beta) {
+  double alpha = x[0];
+  if (L <= 1) {
+    *beta = alpha;
+    return 0.0;
+  }
+  double sigma = norm2_scaled(L - 1, x + inc, inc);
+  if (sigma == 0.0) {
+    *beta = alpha;
+    return 0.0;
+  }
+  double s = (alpha < 0.0) ? -1.0 : 1.0;
+#if ORACLE_MUTANT == 2
+  double b = s * hypot(alpha, sigma); /* planted: wrong sign of beta */
+#else
+  double b = -s * hypot(alpha, sigma);
+#endif
+  double tau = (b - alpha) / b;
+  double d = alpha - b;
+  for (int64_t i = 1; i < L; ++i) x[i * inc] = x[i * inc] / d;
+  *beta = b;
+  return tau;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Symmetric band reduction                                                  */
+/* ------------------------------------------------------------------------ */
+
+int oracle_sy2sb(int64_t n, int64_t w, int64_t ncols, double *A, int64_t lda,
+                 double *tau) {
+  if (n < 0) return -1;
+  if (w < 1) return -2;
+  if (n > 0 && A == NULL) return -4;
+  if (lda < (n > 1 ? n : 1)) return -5;
+  if (n > w && tau == NULL) return -6;
+  if (n <= w) return 0;
+
+  for (int64_t c = 0; c < n - w; ++c) tau[c] = 0.0;
+  int64_t nref = n - w - 1; /* reflector columns c = 0 .. n-w-2 */
+  if (ncols >= 0 && ncols < nref) nref = ncols;
+  if (nref <= 0) return 0;
+
+  /* Full symmetric working copy S (n x n, column-major, ld n): the lower
+   * triangle of A mirrored.  The rank-2 update below keeps it exactly
+   * symmetric, so A2 v can be formed as column dots. */
+  double *S = (double *)malloc(sizeof(double) * (size_t)n * (size_t)n);
+  double *v = (double *)malloc(sizeof(double) * (size_t)n);
+  double *p = (double *)malloc(sizeof(double) * (size_t)n);
+  double *q = (double *)malloc(sizeof(double) * (size_t)n);
+  if (!S || !v || !p || !q) {
+    free(S); free(v); free(p); free(q);
+    return 2;
+  }
+#pragma omp parallel for schedule(static)
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t i = j; i < n; ++i) {
+      S[i + j * n] = A[i + j * lda];
+      S[j + i * n] = A[i + j * lda];
+    }
+
+  for (int64_t c = 0; c < nref; ++c) {
+    const int64_t r = c + w;   /* first row of the reflector */
+    const int64_t L = n - r;   /* its length */
+    double beta;
+    double tc = oracle_house(L, S + r + c * n, 1, &beta);
+    v[0] = 1.0;
+    for (int64_t i = 1; i < L; ++i) v[i] = S[r + i + c * n];
+
+    if (tc != 0.0) {
+      double *A2 = S + r + r * n; /* trailing block, ld n */
+      /* p = tau * A2 v */
+#pragma omp parallel for schedule(static)
+      for (int64_t i = 0; i < L; ++i) {
+        const double *col = A2 + i * n;
+        double s = 0.0;
+#if ORACLE_MUTANT == 4
+        for (int64_t k = 1; k < L; ++k) s += col[k] * v[k]; /* planted: v[0] dropped */
+#else
+        for (int64_t k = 0; k < L; ++k) s += col[k] * v[k];
+#endif
+        p[i] = tc * s;
+      }
+      /* K = tau/2 * p^T v ; q = p - K v */
+      double pv = 0.0;
+      for (int64_t i = 0; i < L; ++i) pv += p[i] * v[i];
+#if ORACLE_MUTANT == 1
+      double K = tc * pv; /* planted: the factor 1/2 dropped */
+#else
+      double K = 0.5 * tc * pv;
+#endif
+      for (int64_t i = 0; i < L; ++i) q[i] = p[i] - K * v[i];
+      /* A2 -= v q^T + q v^T  (both triangles, stays symmetric) */
+#pragma omp parallel for schedule(static)
+      for (int64_t k = 0; k < L; ++k) {
+        double *col = A2 + k * n;
+        const double vk = v[k], qk = q[k];
+        for (int64_t i = 0; i < L; ++i) col[i] -= v[i] * qk + q[i] * vk;
+      }
+#if ORACLE_MUTANT != 3
+      /* in-band columns c+1 .. r-1: H from the left only, rows r .. n-1 */
+#pragma omp parallel for schedule(static)
+      for (int64_t j = c + 1; j < r; ++j) {
+        double *col = S + r + j * n;
+        double s = 0.0;
+        for (int64_t i = 0; i < L; ++i) s += v[i] * col[i];
+        const double f = tc * s;
+        for (int64_t i = 0; i < L; ++i) {
+          col[i] -= f * v[i];
+          S[j + (r + i) * n] = col[i];
+        }
+      }
+#endif
+    }
+    S[r + c * n] = beta;
+    tau[c] = tc;
+  }
+
+#pragma omp parallel for schedule(static)
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t i = j; i < n; ++i) A[i + j * lda] = S[i + j * n];
+
+  free(S); free(v); free(p); free(q);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* General matrix to upper triangular-band                                   */
+/* ------------------------------------------------------------------------ */
+
+int oracle_ge2gb(int64_t m, int64_t n, int64_t w, int64_t ncols, double *A,
+                 int64_t lda, double *tauq, double *taup) {
+  if (m < 0) return -1;
+  if (n < 0) return -2;
+  if (m < n) return -1;
+  if (w < 1) return -3;
+  if (n > 0 && A == NULL) return -5;
+  if (lda < (m > 1 ? m : 1)) return -6;
+  if (n > 0 && tauq == NULL) return -7;
+  if (n > 0 && taup == NULL) return -8;
+  if (n == 0) return 0;
+
+  for (int64_t c = 0; c < n; ++c) tauq[c] = taup[c] = 0.0;
+  int64_t nsteps = n;
+  if (ncols >= 0 && ncols < nsteps) nsteps = ncols;
+
+  double *u = (double *)malloc(sizeof(double) * (size_t)(m > n ? m : n));
+  double *s = (double *)malloc(sizeof(double) * (size_t)m);
+  if (!u || !s) {
+    free(u); free(s);
+    return 2;
+  }
+
+  for (int64_t c = 0; c < nsteps; ++c) {
+    /* left reflector: column c, rows c .. m-1 */
+    {
+      const int64_t L = m - c;
+      double beta;
+      double tq = oracle_house(L, A + c + c * lda, 1, &beta);
+      u[0] = 1.0;
+      for (int64_t i = 1; i < L; ++i) u[i] = A[c + i + c * lda];
+      if (tq != 0.0) {
+#if ORACLE_MUTANT == 6
+        const int64_t jend = (c + w < n) ? c + w : n; /* planted: far columns skipped */
+#else
+        const int64_t jend = n;
+#endif
+#pragma omp parallel for schedule(static)
+        for (int64_t j = c + 1; j < jend; ++j) {
+          double *col = A + c + j * lda;
+          double d = 0.0;
+          for (int64_t i = 0; i < L; ++i) d += u[i] * col[i];
+          const double f = tq * d;
+          for (int64_t i = 0; i < L; ++i) col[i] -= f * u[i];
+        }
+      }
+      A[c + c * lda] = beta;
+      tauq[c] = tq;
+    }
+    /* right reflector: row c, columns c+w .. n-1 */
+    if (c <= n - w - 2) {
+      const int64_t c0 = c + w;
+      const int64_t L = n - c0;
+      double gamma;
+      double tp = oracle_house(L, A + c + c0 * lda, lda, &gamma);
+      u[0] = 1.0;
+      for (int64_t k = 1; k < L; ++k) u[k] = A[c + (c0 + k) * lda];
+      if (tp != 0.0) {
+#if ORACLE_MUTANT == 5
+        const int64_t r0 = c; /* planted: row c itself updated */
+#else
+        const int64_t r0 = c + 1;
+#endif
+        const int64_t nr = m - r0;
+        int nt = oracle_threads();
+        int64_t chunk = (nr + nt - 1) / nt;
+        if (chunk < 64) chunk = 64;
+#pragma omp parallel for schedule(static)
+        for (int64_t r1 = 0; r1 < nr; r1 += chunk) {
+          const int64_t r2 = (r1 + chunk < nr) ? r1 + chunk : nr;
+          double *sr = s + r0;
+          for (int64_t r = r1; r < r2; ++r) sr[r] = 0.0;
+          for (int64_t k = 0; k < L; ++k) {
+            const double *col = A + r0 + (c0 + k) * lda;
+            const double uk = u[k];
+            for (int64_t r = r1; r < r2; ++r) sr[r] += col[r] * uk;
+          }
+          for (int64_t k = 0; k < L; ++k) {
+            double *col = A + r0 + (c0 + k) * lda;
+            const double f = tp * u[k];
+            for (int64_t r = r1; r < r2; ++r) col[r] -= sr[r] * f;
+          }
+        }
+      }
+      A[c + c0 * lda] = gamma;
+      taup[c] = tp;
+    }
+  }
+  free(u); free(s);
+  return 0;
+}
