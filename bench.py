@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Benchmark of the SY2SB hot path on one MI355X.
+
+One step = one complete reduction (panel QR + T factor + left update + SYMM +
+small GEMMs + SYR2K for every panel, with look-ahead) of the workload
+``sy2sb_n16384_w128``: n = 16384, w = b = 128, A = Q diag(lam) Q^T with a
+graded spectrum lam_i = +-10^(-6 i / n) and Haar Q (seeded, built on the GPU).
+The matrix is restored from a pristine device copy before every step, outside
+the timed events; inputs are resident in HBM when timing starts.
+
+value = nominal 4 n^3 / 3 flops / median step time (the paper's flop rule,
+Sec. 4), FP64.  Also reported: the FP32 and split-FP32 trailing-update forms on
+the same matrix, accuracy of the timed result, the dominant kernel against
+the FP64 matrix-core peak, and the CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+       [--no-forms] [--no-cpu-baseline] [--profile-only]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SY2SB/GE2GB GFLOP/s, FP64 vs split-FP32 at n=16384; % MFMA peak; backward err"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split32": 157.3}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def nominal_flops(p):
+    if "m" in p:  # ge2gb: 4 (m n^2 - n^3 / 3)   (Sec. 3.1)
+        m, n = p["m"], p["n"]
+        return 4.0 * (m * n * n - n ** 3 / 3.0)
+    n = p["n"]
+    return 4.0 * n ** 3 / 3.0  # Sec. 2.1
+
+
+def time_steps(run, restore, steps, stream):
+    import torch
+
+    times = []
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    for _ in range(steps):
+        restore()
+        torch.cuda.synchronize()
+        start.record(stream)
+        run()
+        end.record(stream)
+        torch.cuda.synchronize()
+        times.append(start.elapsed_time(end))
+    return times
+
+
+def cpu_baseline(p, A_dev):
+    """The oracle as it stands, on the first k reflector columns of the same
+    matrix (a bounded sample), rated with the same per-column flop model."""
+    import numpy as np
+
+    import oracle
+
+    orc = oracle.get()
+    n, w = p["n"], p["w"]
+    A = A_dev.cpu().numpy()
+    t0 = time.perf_counter()
+    orc.sy2sb(A, w, ncols=4)
+    t4 = time.perf_counter() - t0
+    per_col = max(t4 / 4.0, 1e-3)
+    k = int(max(4, min(n - w - 1, 15.0 / per_col)))
+    t0 = time.perf_counter()
+    orc.sy2sb(A, w, ncols=k)
+    dt = time.perf_counter() - t0
+    flops = sum(4.0 * (n - c - w) ** 2 for c in range(k))
+    return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": orc.threads(), "kind": "oracle",
+            "sample": f"first {k} of {n - w - 1} reflector columns of the n={n}, w={w} matrix "
+                      f"(4 j^2 flops per column of trailing order j), {dt:.1f} s incl. the "
+                      f"oracle's full-matrix copy in and out"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="sy2sb_n16384_w128")
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="warm up and run the steps only (for rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only; this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1709_00302_amd as br
+    from paper_1709_00302_amd import inputs, metrics
+
+    br.load()
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    log(f"bench: building workload {args.workload} on the GPU")
+    p = inputs.make_on_device(args.workload, device="cuda")
+    A0 = p["A"]
+    A = torch.empty_like(A0)  # same column-major strides
+    A.copy_(A0)
+    assert A.stride(0) == 1
+    n, w, b = p["n"], p["w"], p["b"]
+    is_ge = "m" in p
+    flops = nominal_flops(p)
+
+    def restore():
+        A.copy_(A0)
+
+    out = {}
+
+    def runner(prec):
+        if is_ge:
+            def run():
+                out["tau"] = br.ge2gb(A, w, b, prec=prec)
+        else:
+            def run():
+                out["tau"] = br.sy2sb(A, w, b, prec=prec)
+        return run
+
+    run64 = runner("fp64")
+    log(f"bench: warmup {args.warmup}")
+    for _ in range(args.warmup):
+        restore()
+        run64()
+    torch.cuda.synchronize()
+    log(f"bench: timing {args.steps} steps")
+    t_wall = time.perf_counter()
+    times = time_steps(run64, restore, args.steps, stream)
+    t_wall = time.perf_counter() - t_wall
+    ms = statistics.median(times)
+    gflops = flops / (ms / 1e3) / 1e9
+    log(f"bench: fp64 steps ms = {[round(t, 2) for t in times]}  -> {gflops:.1f} GFLOP/s")
+    if args.profile_only:
+        print(json.dumps({"metric": METRIC, "value": gflops, "unit": "GFLOP/s", "ms_per_step": ms}))
+        return
+
+    # accuracy of the (last) timed result
+    acc = {}
+    if not args.no_accuracy:
+        log("bench: accuracy of the FP64 result")
+        if is_ge:
+            tq, tp = out["tau"]
+            acc = metrics.ge2gb_errors(A0, A, tq, tp, w, svd=False)
+        else:
+            acc = metrics.sy2sb_errors(A0, torch.tril(A), out["tau"], w, eig=False)
+        acc = {k: v for k, v in acc.items() if v is not None}
+
+    # dominant kernel: one more step with per-launch events
+    log("bench: per-kernel profile step")
+    restore()
+    torch.cuda.synchronize()
+    br.bandred_profile_enable(True)
+    run64()
+    torch.cuda.synchronize()
+    prof = br.bandred_profile_read()
+    br.bandred_profile_enable(False)
+    dom = max((k for k in prof if prof[k]["flops"] > 0), key=lambda k: prof[k]["ms"])
+    d = prof[dom]
+    achieved = d["flops"] / (d["ms"] / 1e3) / 1e12
+    roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_TFLOPS["fp64"],
+                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["fp64"], "traffic": None,
+                "avg_launch_ms": d["ms"] / max(d["launches"], 1), "launches": d["launches"]}
+    breakdown = {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
+                     "tflops": (v["flops"] / (v["ms"] / 1e3) / 1e12) if v["ms"] > 0 and v["flops"] > 0 else None}
+                 for k, v in prof.items() if v["launches"]}
+
+    forms = {}
+    if not args.no_forms:
+        for prec in ("fp32", "split32"):
+            log(f"bench: form {prec}")
+            run = runner(prec)
+            restore()
+            run()
+            torch.cuda.synchronize()
+            tt = time_steps(run, restore, max(2, args.steps // 2), stream)
+            m2 = statistics.median(tt)
+            f = {"gflops": flops / (m2 / 1e3) / 1e9, "ms_per_step": m2,
+                 "speedup_vs_fp64": ms / m2}
+            if not args.no_accuracy:
+                if is_ge:
+                    tq, tp = out["tau"]
+                    e = metrics.ge2gb_errors(A0, A, tq, tp, w, svd=False)
+                else:
+                    e = metrics.sy2sb_errors(A0, torch.tril(A), out["tau"], w, eig=False)
+                f["backward"] = e["backward"]
+            forms[prec] = f
+
+    cpu = None
+    if not args.no_cpu_baseline and not is_ge:
+        log("bench: cpu baseline (oracle, bounded sample)")
+        cpu = cpu_baseline(p, A0)
+
+    res = {
+        "metric": METRIC,
+        "value": gflops,
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "w": w, "b": b,
+                   **({"m": p["m"]} if is_ge else {}), "prec": "fp64", "lookahead": True,
+                   "input": p["kind"] + (f", {p.get('spectrum')} spectrum" if "spectrum" in p else "")
+                   + f", seed {p['seed']}"},
+        "pct_fp64_peak": 100.0 * gflops / 1e3 / PEAK_TFLOPS["fp64"],
+        "step_ms_all": [round(t, 3) for t in times],
+        "timed_wall_s": t_wall,
+        "accuracy": acc,
+        "roofline": roofline,
+        "kernels": breakdown,
+        "forms": forms,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

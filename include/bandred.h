@@ -1,0 +1,147 @@
+/*
+ * bandred.h -- C ABI of the MI355X (gfx950) band-reduction library.
+ *
+ * The library computes the first stage of two-stage dense eigen- and
+ * singular-value solvers: the blocked two-sided Householder reduction of
+ *   - a dense symmetric matrix to symmetric band form with bandwidth w
+ *     (Sec. 2.1 of Rodriguez-Sanchez et al., "Look-ahead in the two-sided
+ *     reduction to compact band forms", eqs. updateA0 to updateA2syr2k), and
+ *   - a dense general m x n matrix (m >= n) to upper triangular-band form with
+ *     upper bandwidth w (Sec. 3.1, eqs. updateB to updateD).
+ * b is the algorithmic block size (panel width), 1 <= b <= w (Sec. 2.1).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are FP64, column-major, leading dimension lda (in elements).
+ *   - Unless a name ends in _host, every matrix and tau pointer is a DEVICE
+ *     pointer (HIP global memory on the current device).  The caller owns all
+ *     of them; the library keeps no pointer after the call returns.
+ *   - Reflectors use the LAPACK convention H = I - tau v v^T with v[0] = 1
+ *     implicit; the product of the reflectors of one panel is I - V T V^T
+ *     with T upper triangular (compact WY).  The paper writes Q = I + W Y^T;
+ *     the two agree with Y = V and W = -V T.
+ *   - The library allocates its own device workspace (cached per device and
+ *     grown on demand).  Calls on the same device are ordered on that
+ *     workspace: a call waits (on its stream) for the previous call's work.
+ *   - Return value: 0 on success; -i when argument i (1-based) is invalid;
+ *     a positive BANDRED_ERR_* code on a runtime failure.
+ */
+#ifndef BANDRED_H
+#define BANDRED_H
+
+#include <stdint.h>
+
+#ifndef BANDRED_API
+#define BANDRED_API __attribute__((visibility("default")))
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  BANDRED_OK = 0,
+  BANDRED_ERR_HIP = 1,         /* a HIP runtime call failed */
+  BANDRED_ERR_ALLOC = 2,       /* device workspace allocation failed */
+  BANDRED_ERR_UNSUPPORTED = 3, /* device or problem shape not supported */
+  BANDRED_ERR_TIMEOUT = 4      /* a kernel's bounded inter-workgroup wait gave up */
+};
+
+/* Arithmetic of the trailing-update products (the SYMM/SYR2K of eqs.
+ * updateA2symm/updateA2syr2k, the left update of eq. updateA1 and the
+ * GEMM pairs of eqs. updateCD/updateD).  Panels, tau and T are FP64 always. */
+typedef enum {
+  BANDRED_FP64 = 0,           /* FP64 MFMA, FP64 accumulation */
+  BANDRED_FP32_UPDATE = 1,    /* operands rounded to FP32, FP32 MFMA and accumulation,
+                                 result added to the FP64 matrix */
+  BANDRED_SPLIT32_UPDATE = 2  /* x = hi + lo (both FP32); hi*hi + hi*lo + lo*hi on FP32
+                                 MFMA with FP32 accumulation, summed in FP64 */
+} bandred_prec_t;
+
+/* Optional knobs for the _ex entry points (pass NULL for defaults). */
+typedef struct {
+  int lookahead;      /* 1 (default): factor the next panel on a second stream while
+                         the rest of the trailing matrix is updated (Sec. 2.2);
+                         0: one stream, strictly sequential (debug / comparison) */
+  int panel_rows;     /* rows of the panel held per workgroup; 0 = automatic */
+  int reserved[6];    /* must be zero */
+} bandred_opts_t;
+
+/* Symmetric A (n x n) to symmetric band form, bandwidth w, block size b
+ * (Sec. 2.1; look-ahead variants of Sec. 2.2).
+ *   n    order of A, n >= 0                                      (arg 1)
+ *   w    bandwidth, w >= 1                                       (arg 2)
+ *   b    block size, 1 <= b <= w                                 (arg 3)
+ *   A    device, lda x n; only the LOWER triangle is read and written; the
+ *        strict upper triangle is never referenced                (arg 4)
+ *   lda  >= max(1, n)                                            (arg 5)
+ *   tau  device, n - w entries when n > w (unused otherwise)      (arg 6)
+ * On return B(i,j), 0 <= i-j <= w, holds the band; column c (0 <= c <= n-w-2)
+ * holds v[1:] of reflector c in rows c+w+1 .. n-1 (v[0] = 1 at row c+w is
+ * implicit) and tau[c] its scalar; tau[n-w-1] = 0.  Q = H_0 H_1 ... and
+ * B = Q^T A Q.  When n <= w+1 the matrix is already banded: A is untouched and
+ * tau is zero-filled.  Runs on the null stream and returns after completion. */
+BANDRED_API int bandred_sy2sb(int64_t n, int64_t w, int64_t b, double *A, int64_t lda,
+                  double *tau);
+
+/* General A (m x n, m >= n) to upper triangular-band form, upper bandwidth w,
+ * block size b (Sec. 3.1).
+ *   m, n  m >= n >= 0                                   (args 1, 2)
+ *   w     >= 1; b: 1 <= b <= w                          (args 3, 4)
+ *   A     device, lda x n                               (arg 5)
+ *   lda   >= max(1, m)                                  (arg 6)
+ *   tauq, taup  device, n entries each                  (args 7, 8)
+ * On return B(i,j), 0 <= j-i <= w, holds the band.  Left reflector c
+ * (c < n) has v[1:] in A(c+1:m-1, c) and scalar tauq[c] (0 when m-c < 2);
+ * right reflector c (c <= n-w-2) has u[1:] in A(c, c+w+1:n-1), u[0] = 1 at
+ * column c+w, scalar taup[c]; the other taup entries are 0.  U = H_0 H_1 ...,
+ * V = G_0 G_1 ..., B = U^T A V.  Null stream, returns after completion. */
+BANDRED_API int bandred_ge2gb(int64_t m, int64_t n, int64_t w, int64_t b, double *A,
+                  int64_t lda, double *tauq, double *taup);
+
+/* As bandred_sy2sb with a precision form, options and a stream
+ * (hipStream_t, NULL = null stream).  Asynchronous: returns once the work is
+ * enqueued (argument errors are reported synchronously).
+ * Extra arguments: prec (arg 7), opts (arg 8, may be NULL), stream (arg 9). */
+BANDRED_API int bandred_sy2sb_ex(int64_t n, int64_t w, int64_t b, double *A, int64_t lda,
+                     double *tau, int prec, const bandred_opts_t *opts,
+                     void *stream);
+
+/* As bandred_ge2gb with prec (arg 9), opts (arg 10) and stream (arg 11);
+ * asynchronous like bandred_sy2sb_ex. */
+BANDRED_API int bandred_ge2gb_ex(int64_t m, int64_t n, int64_t w, int64_t b, double *A,
+                     int64_t lda, double *tauq, double *taup, int prec,
+                     const bandred_opts_t *opts, void *stream);
+
+/* Many independent symmetric matrices of uneven orders reduced in one
+ * persistent launch (not in the paper; same per-matrix result as
+ * bandred_sy2sb).
+ *   count  number of matrices, >= 0                                  (arg 1)
+ *   n      HOST array of count orders                                (arg 2)
+ *   w, b   bandwidth and block size for all matrices, 1 <= b <= w    (args 3, 4)
+ *   A      HOST array of count DEVICE pointers                       (arg 5)
+ *   lda    HOST array of count leading dimensions                    (arg 6)
+ *   tau    HOST array of count DEVICE pointers (n[i] - w entries each,
+ *          may be NULL for matrices with n[i] <= w)                   (arg 7)
+ *   prec   BANDRED_FP64 or BANDRED_FP32_UPDATE                       (arg 8)
+ *   stream hipStream_t or NULL                                       (arg 9)
+ * Asynchronous like the _ex calls. */
+BANDRED_API int bandred_sy2sb_batched(int64_t count, const int64_t *n, int64_t w, int64_t b,
+                          double *const *A, const int64_t *lda,
+                          double *const *tau, int prec, void *stream);
+
+/* Static description of a status code. */
+BANDRED_API const char *bandred_status_string(int status);
+
+/* Per-kernel-class device time of the most recent call (diagnostics).
+ * When enabled (on != 0) every launch is bracketed by HIP events on the
+ * stream it runs on; bandred_profile_read fills up to cap entries of
+ * {ms, flops, launches} triples (3 doubles per class, classes in the order of
+ * bandred_profile_name) and returns the number of classes. */
+BANDRED_API int bandred_profile_enable(int on);
+BANDRED_API int bandred_profile_read(double *out, int cap);
+BANDRED_API const char *bandred_profile_name(int cls);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,221 @@
+"""Python binding of ``libbandred.so``, the gfx950 band-reduction library.
+
+Argument marshalling only: every step of the reductions runs in the HIP
+kernels of the shared library.  PyTorch supplies device memory and streams.
+There is no CPU fallback: if the library is not built, importing the binding
+works but every call raises ``BandredUnavailable``.
+
+Raw entry points carry the C names (``bandred_sy2sb`` ...) and take integers
+(device addresses); the helpers ``sy2sb`` / ``ge2gb`` / ``sy2sb_batched``
+take torch tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbandred.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "bandred.h")
+
+FP64, FP32_UPDATE, SPLIT32_UPDATE = 0, 1, 2
+PREC_NAMES = {"fp64": FP64, "fp32": FP32_UPDATE, "split32": SPLIT32_UPDATE}
+
+
+class BandredUnavailable(RuntimeError):
+    pass
+
+
+class BandredError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn} returned {code}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("lookahead", ctypes.c_int), ("panel_rows", ctypes.c_int),
+                ("reserved", ctypes.c_int * 6)]
+
+
+_i64 = ctypes.c_int64
+_vp = ctypes.c_void_p
+_lib = None
+
+
+def declared_symbols(header: str = HEADER) -> list[str]:
+    """Names of the functions ``include/bandred.h`` declares."""
+    txt = open(header).read()
+    return sorted(set(re.findall(r"BANDRED_API\s+[\w\s\*]*?\b(bandred_\w+)\s*\(", txt)))
+
+
+def load(path: str = LIB_PATH):
+    """Load the shared library (once)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise BandredUnavailable(
+            f"{path} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(path)
+    lib.bandred_sy2sb.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp]
+    lib.bandred_ge2gb.argtypes = [_i64, _i64, _i64, _i64, _vp, _i64, _vp, _vp]
+    lib.bandred_sy2sb_ex.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, ctypes.c_int,
+                                     ctypes.POINTER(Opts), _vp]
+    lib.bandred_ge2gb_ex.argtypes = [_i64, _i64, _i64, _i64, _vp, _i64, _vp, _vp, ctypes.c_int,
+                                     ctypes.POINTER(Opts), _vp]
+    lib.bandred_sy2sb_batched.argtypes = [_i64, ctypes.POINTER(_i64), _i64, _i64,
+                                          ctypes.POINTER(_vp), ctypes.POINTER(_i64),
+                                          ctypes.POINTER(_vp), ctypes.c_int, _vp]
+    lib.bandred_status_string.argtypes = [ctypes.c_int]
+    lib.bandred_status_string.restype = ctypes.c_char_p
+    lib.bandred_profile_enable.argtypes = [ctypes.c_int]
+    lib.bandred_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+    lib.bandred_profile_name.argtypes = [ctypes.c_int]
+    lib.bandred_profile_name.restype = ctypes.c_char_p
+    for name in ("bandred_sy2sb", "bandred_ge2gb", "bandred_sy2sb_ex", "bandred_ge2gb_ex",
+                 "bandred_sy2sb_batched", "bandred_profile_enable", "bandred_profile_read"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def status_string(code: int) -> str:
+    return load().bandred_status_string(int(code)).decode()
+
+
+def _check(fn: str, rc: int) -> int:
+    if rc != 0:
+        raise BandredError(fn, rc, status_string(rc))
+    return rc
+
+
+# ---- raw entry points (same names as the C ABI) ---------------------------
+
+def bandred_sy2sb(n, w, b, A, lda, tau) -> int:
+    return load().bandred_sy2sb(n, w, b, A, lda, tau)
+
+
+def bandred_ge2gb(m, n, w, b, A, lda, tauq, taup) -> int:
+    return load().bandred_ge2gb(m, n, w, b, A, lda, tauq, taup)
+
+
+def bandred_sy2sb_ex(n, w, b, A, lda, tau, prec=FP64, opts=None, stream=None) -> int:
+    return load().bandred_sy2sb_ex(n, w, b, A, lda, tau, prec,
+                                   ctypes.byref(opts) if opts is not None else None, stream)
+
+
+def bandred_ge2gb_ex(m, n, w, b, A, lda, tauq, taup, prec=FP64, opts=None, stream=None) -> int:
+    return load().bandred_ge2gb_ex(m, n, w, b, A, lda, tauq, taup, prec,
+                                   ctypes.byref(opts) if opts is not None else None, stream)
+
+
+def bandred_sy2sb_batched(count, n, w, b, A, lda, tau, prec=FP64, stream=None) -> int:
+    arr_n = (_i64 * count)(*[int(x) for x in n])
+    arr_a = (_vp * count)(*[int(x) if x else None for x in A])
+    arr_l = (_i64 * count)(*[int(x) for x in lda])
+    arr_t = (_vp * count)(*[int(x) if x else None for x in tau])
+    return load().bandred_sy2sb_batched(count, arr_n, w, b, arr_a, arr_l, arr_t, prec, stream)
+
+
+def bandred_status_string(code: int) -> str:
+    return status_string(code)
+
+
+def bandred_profile_enable(on: bool) -> int:
+    return load().bandred_profile_enable(1 if on else 0)
+
+
+def bandred_profile_read() -> dict:
+    lib = load()
+    buf = (ctypes.c_double * 96)()
+    ncls = lib.bandred_profile_read(buf, 96)
+    out = {}
+    for c in range(ncls):
+        name = lib.bandred_profile_name(c).decode()
+        out[name] = {"ms": buf[3 * c], "flops": buf[3 * c + 1], "launches": int(buf[3 * c + 2])}
+    return out
+
+
+def bandred_profile_name(cls: int) -> str:
+    return load().bandred_profile_name(cls).decode()
+
+
+# ---- torch helpers ---------------------------------------------------------
+
+def _colmajor_ld(A, rows: int) -> int:
+    import torch
+
+    if A.dtype != torch.float64 or not A.is_cuda:
+        raise TypeError("A must be a float64 CUDA tensor")
+    if A.dim() != 2:
+        raise ValueError("A must be 2-D")
+    if A.shape[1] > 1 and A.stride(0) != 1:
+        raise ValueError("A must be column-major (stride(0) == 1); use A.T.contiguous().T")
+    ld = A.stride(1) if A.shape[1] > 1 else max(rows, 1)
+    return max(ld, 1)
+
+
+def _stream_handle(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def sy2sb(A, w: int, b: int | None = None, prec="fp64", lookahead: bool = True,
+          panel_rows: int = 0, stream=None, tau=None):
+    """Reduce the symmetric column-major CUDA tensor ``A`` (lower triangle) to
+    band width ``w`` in place; returns tau (device tensor)."""
+    import torch
+
+    n = A.shape[0]
+    b = w if b is None else b
+    lda = _colmajor_ld(A, n)
+    if tau is None:
+        tau = torch.zeros(max(n - w, 1), dtype=torch.float64, device=A.device)
+    p = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
+    o = Opts(1 if lookahead else 0, int(panel_rows))
+    rc = bandred_sy2sb_ex(n, w, b, A.data_ptr(), lda, tau.data_ptr(), p, o, _stream_handle(stream))
+    _check("bandred_sy2sb_ex", rc)
+    return tau[: max(n - w, 0)]
+
+
+def ge2gb(A, w: int, b: int | None = None, prec="fp64", panel_rows: int = 0, stream=None):
+    """Reduce the column-major CUDA tensor ``A`` (m >= n) to upper
+    triangular-band width ``w`` in place; returns (tauq, taup)."""
+    import torch
+
+    m, n = A.shape
+    b = w if b is None else b
+    lda = _colmajor_ld(A, m)
+    tauq = torch.zeros(max(n, 1), dtype=torch.float64, device=A.device)
+    taup = torch.zeros(max(n, 1), dtype=torch.float64, device=A.device)
+    p = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
+    o = Opts(1, int(panel_rows))
+    rc = bandred_ge2gb_ex(m, n, w, b, A.data_ptr(), lda, tauq.data_ptr(), taup.data_ptr(), p, o,
+                          _stream_handle(stream))
+    _check("bandred_ge2gb_ex", rc)
+    return tauq[:n], taup[:n]
+
+
+def sy2sb_batched(mats, w: int, b: int | None = None, prec="fp64", stream=None):
+    """Reduce a list of symmetric column-major CUDA tensors in one call;
+    returns the list of tau tensors."""
+    import torch
+
+    b = w if b is None else b
+    ns, ptrs, lds, taus = [], [], [], []
+    for A in mats:
+        n = A.shape[0]
+        ns.append(n)
+        ptrs.append(A.data_ptr())
+        lds.append(_colmajor_ld(A, n))
+        t = torch.zeros(max(n - w, 1), dtype=torch.float64, device=A.device)
+        taus.append(t)
+    p = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
+    rc = bandred_sy2sb_batched(len(mats), ns, w, b, ptrs, lds, [t.data_ptr() for t in taus], p,
+                               _stream_handle(stream))
+    _check("bandred_sy2sb_batched", rc)
+    return [t[: max(n - w, 0)] for t, n in zip(taus, ns)]

@@ -1,0 +1,88 @@
+// common.hpp -- shared definitions of the gfx950 band-reduction library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/bandred.h"
+
+namespace br {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;   // threads per workgroup for every tiled kernel
+constexpr int kNbMax = 128;     // widest panel (block size b) supported
+constexpr int kBK = 16;         // k-depth of one LDS stage of the GEMM kernels
+
+// Trailing-update arithmetic (matches bandred_prec_t).
+enum Prec { P_F64 = 0, P_F32 = 1, P_SPLIT = 2 };
+
+// Operand access patterns of the GEMM kernels.
+//   A_N:   op(A)(i,k) = A[i + k*lda]
+//   A_T:   op(A)(i,k) = A[k + i*lda]
+//   A_SYM: op(A)(i,k) = A[max(i,k) + min(i,k)*lda]  (symmetric, lower stored)
+//   B_N:   op(B)(k,j) = B[k + j*ldb]
+//   B_T:   op(B)(k,j) = B[j + k*ldb]
+//   B_TROT:op(B)(k,j) = B[j + ((k + rot) mod K)*ldb]
+enum OpA { A_N = 0, A_T = 1, A_SYM = 2 };
+enum OpB { B_N = 0, B_T = 1, B_TROT = 2 };
+
+// Epilogues.
+//   E_AXPBY:  C = alpha*acc + beta*C  (C not read when beta == 0)
+//   E_PART:   part[z] = acc           (split-K partial, column-major ld M)
+//   E_SYR2K:  C -= acc on the lower triangle (row >= col) of a column range
+enum Epi { E_AXPBY = 0, E_PART = 1, E_SYR2K = 2 };
+
+struct GemmDesc {
+  int M, N, K;
+  const double *A;
+  int64_t lda;
+  const double *B;
+  int64_t ldb;
+  double *C;
+  int64_t ldc;
+  double alpha, beta;
+  int kchunk;      // k-range handled by one blockIdx.z (multiple of kBK)
+  double *part;    // E_PART output: part + z*M*N, column-major ld M
+  int rot;         // B_TROT rotation
+  int c0, c1;      // E_SYR2K: columns [c0, c1) of C, rows >= c0
+};
+
+struct PanelDesc {
+  double *P;        // panel, element (r,k) at P[r*rs + k*cs]
+  int64_t ldp;      // the stride that is not 1
+  int m, nb, R;     // rows, columns, rows per workgroup
+  double *V;        // explicit V (m x nb, column-major, unit diagonal, zero above)
+  int64_t ldv;
+  double *tau;      // nb scalars
+  double *part;     // [2][gridDim.x][kNbMax] partial dot products
+  double *piv;      // [kNbMax][kNbMax] pivot rows
+  unsigned *counter;// arrival counter, zero at launch
+  int *status;      // set to 4 (timeout) if a wait gives up
+  int *abort_flag;  // raised by the first workgroup that gives up
+  long long timeout_ticks;  // bound of one wait, in s_memrealtime ticks
+};
+
+}  // namespace br
+
+#define BR_HIP_CHECK(expr)                                  \
+  do {                                                      \
+    hipError_t _e = (expr);                                 \
+    if (_e != hipSuccess) return br::hip_fail(_e, #expr);   \
+  } while (0)
+
+namespace br {
+int hip_fail(hipError_t e, const char *what);
+
+// host-side launchers (defined in gemm.hip / panel.hip)
+int launch_gemm(int opa, int opb, int epi, int prec, const GemmDesc &d, int ksplit,
+                hipStream_t s);
+int launch_reduce_partials(const double *part, int ksplit, int M, int N, double alpha,
+                           double *C, int64_t ldc, double beta, hipStream_t s);
+int launch_panel(bool rowmajor, const PanelDesc &d, int nwg, hipStream_t s);
+int launch_larft(const double *S, int ldS, const double *tau, int nb, double *T, int ldT,
+                 hipStream_t s);
+int launch_fill(double *p, int64_t count, double v, hipStream_t s);
+int launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t s);
+int panel_lds_bytes(int R, int nb);
+}  // namespace br

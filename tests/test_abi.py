@@ -1,0 +1,80 @@
+"""The C ABI boundary without a GPU: the library loads, exports every symbol
+the header declares, and rejects invalid arguments before any device work."""
+import ctypes
+
+import pytest
+
+import paper_1709_00302_amd as br
+
+
+def test_header_declares_the_boundary():
+    names = br.declared_symbols()
+    for n in ("bandred_sy2sb", "bandred_ge2gb", "bandred_sy2sb_ex", "bandred_ge2gb_ex",
+              "bandred_sy2sb_batched", "bandred_status_string"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = br.load()
+    for n in br.declared_symbols():
+        assert hasattr(lib, n), n
+
+
+def test_binding_has_same_names():
+    for n in br.declared_symbols():
+        assert callable(getattr(br, n)), n
+
+
+FAKE = 0x1000  # never dereferenced: every call below fails argument checks
+
+
+@pytest.mark.parametrize("args,code", [
+    ((-1, 4, 4, FAKE, 1, FAKE), -1),
+    ((10, 0, 1, FAKE, 10, FAKE), -2),
+    ((10, 4, 0, FAKE, 10, FAKE), -3),
+    ((10, 4, 5, FAKE, 10, FAKE), -3),      # b > w (Sec. 2.1 requires b <= w)
+    ((300, 200, 129, FAKE, 300, FAKE), -3),  # b above the widest supported panel
+    ((10, 4, 4, None, 10, FAKE), -4),
+    ((10, 4, 4, FAKE, 9, FAKE), -5),
+    ((10, 4, 4, FAKE, 10, None), -6),
+])
+def test_sy2sb_argument_errors(args, code):
+    assert br.bandred_sy2sb(*args) == code
+
+
+@pytest.mark.parametrize("args,code", [
+    ((-1, 4, 2, 2, FAKE, 1, FAKE, FAKE), -1),
+    ((4, 5, 2, 2, FAKE, 4, FAKE, FAKE), -1),   # m < n unsupported (the paper assumes m >= n)
+    ((5, -1, 2, 2, FAKE, 5, FAKE, FAKE), -2),
+    ((5, 4, 0, 1, FAKE, 5, FAKE, FAKE), -3),
+    ((5, 4, 2, 3, FAKE, 5, FAKE, FAKE), -4),
+    ((5, 4, 2, 2, None, 5, FAKE, FAKE), -5),
+    ((5, 4, 2, 2, FAKE, 4, FAKE, FAKE), -6),
+    ((5, 4, 2, 2, FAKE, 5, None, FAKE), -7),
+    ((5, 4, 2, 2, FAKE, 5, FAKE, None), -8),
+])
+def test_ge2gb_argument_errors(args, code):
+    assert br.bandred_ge2gb(*args) == code
+
+
+def test_ex_precision_and_options_checked():
+    assert br.bandred_sy2sb_ex(10, 4, 4, FAKE, 10, FAKE, 7) == -7
+    o = br.Opts(2, 0)
+    assert br.bandred_sy2sb_ex(10, 4, 4, FAKE, 10, FAKE, 0, o) == -8
+    o = br.Opts(1, 0)
+    o.reserved[3] = 1
+    assert br.bandred_sy2sb_ex(10, 4, 4, FAKE, 10, FAKE, 0, o) == -8
+    assert br.bandred_ge2gb_ex(10, 8, 4, 4, FAKE, 10, FAKE, FAKE, 9) == -9
+
+
+def test_batched_argument_errors():
+    assert br.bandred_sy2sb_batched(1, [-3], 4, 4, [FAKE], [4], [FAKE]) == -2
+    assert br.bandred_sy2sb_batched(1, [10], 4, 4, [FAKE], [9], [FAKE]) == -6
+    assert br.bandred_sy2sb_batched(1, [10], 4, 5, [FAKE], [10], [FAKE]) == -4
+    assert br.bandred_sy2sb_batched(1, [10], 4, 4, [FAKE], [10], [FAKE], prec=2) == -8
+
+
+def test_status_strings():
+    assert br.status_string(0) == "success"
+    assert "argument" in br.status_string(-3)
+    assert "timed out" in br.status_string(4)

@@ -1,0 +1,106 @@
+"""GPU parity of SY2SB (through the C ABI) against the CPU oracle.
+
+Tolerance (FP64): the target bound on the backward error is 1e-14 * n
+(relative to ||A||_F).  Both the GPU result and the oracle are backward-stable
+reductions of the same A, so band entries are compared at 1e-14 * n * ||A||_F
+and the O(1) quantities v (|v_i| <= 1 by construction) and tau (in [1, 2]) at
+1e-14 * n absolute.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1709_00302_amd import inputs, metrics
+from tests.gpu_util import sy_compare, to_device_colmajor
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # (n, w, b, lda_pad, seed)  -- several tiles, ragged tails, V1/V2 partitions
+    (512, 32, 32, 0, 0),
+    (300, 16, 16, 0, 1),
+    (257, 20, 8, 3, 2),     # b < w, 2b <= w (A1 update, panel inside A1)
+    (700, 96, 64, 0, 3),    # 2b > w > b (next panel straddles A1 and A2)
+    (600, 128, 32, 0, 4),   # wide band, narrow panel
+    (1000, 128, 128, 5, 5),
+    (130, 32, 32, 0, 6),
+    (40, 1, 1, 0, 7),       # tridiagonal
+    (97, 7, 3, 0, 8),
+    (2050, 64, 64, 0, 9),
+]
+
+
+def _run(br, A, w, b, lda_pad=0, prec="fp64", lookahead=True):
+    n = A.shape[0]
+    Ad, lda = to_device_colmajor(A, n + lda_pad)
+    tau = br.sy2sb(Ad[:n] if lda_pad else Ad, w, b, prec=prec, lookahead=lookahead)
+    torch.cuda.synchronize()
+    full = Ad.cpu().numpy()
+    return full[:n, :], tau.cpu().numpy(), full
+
+
+@pytest.mark.parametrize("n,w,b,pad,seed", CASES)
+def test_sy2sb_matches_oracle(bandred, orc, n, w, b, pad, seed):
+    print(f"case sy2sb n={n} w={w} b={b} pad={pad} seed={seed}", flush=True)
+    A = inputs.sym_normal(n, 100 + seed)
+    # poison the strict upper triangle: it must be neither read nor written
+    Ain = A.copy()
+    Ain[np.triu_indices(n, 1)] = np.nan
+    Ag, tg, full = _run(bandred, Ain, w, b, pad)
+    assert np.isnan(Ag[np.triu_indices(n, 1)]).all(), "upper triangle was written"
+    if pad:
+        assert np.isnan(full[n:, :]).all(), "rows beyond n were written"
+    Ao, to = orc.sy2sb(A, w)
+    nA = np.linalg.norm(A)
+    db, dr, dt = sy_compare(np.tril(Ag), tg, np.tril(Ao), to, w)
+    tol = 1e-14 * n
+    assert db <= tol * nA, (db, tol * nA)
+    assert dr <= tol, dr
+    assert dt <= tol, dt
+    err = metrics.sy2sb_errors(A, np.tril(Ag), tg, w, eig=False)
+    assert err["backward"] <= 1e-14 * n, err
+
+
+@pytest.mark.parametrize("n,w,b", [(0, 4, 4), (1, 1, 1), (5, 4, 4), (6, 4, 2), (64, 63, 8)])
+def test_sy2sb_degenerate(bandred, orc, n, w, b):
+    A = inputs.sym_normal(max(n, 1), 5)[:n, :n]
+    if n == 0:
+        assert bandred.bandred_sy2sb(0, w, b, 0x1000, 1, 0x1000) == 0
+        return
+    Ag, tg, _ = _run(bandred, A, w, b)
+    Ao, to = orc.sy2sb(A, w)
+    if n <= w + 1:
+        assert np.array_equal(np.tril(Ag), np.tril(A))  # already banded: untouched
+        assert np.all(tg == 0.0)
+    db, dr, dt = sy_compare(np.tril(Ag), tg, np.tril(Ao), to, w)
+    assert max(db, dr, dt) <= 1e-13
+
+
+def test_sy2sb_banded_input_is_exact(bandred):
+    n, w = 300, 12
+    A = inputs.sym_normal(n, 11)
+    i = np.arange(n)
+    A[np.abs(i[:, None] - i[None, :]) > w] = 0.0
+    Ag, tg, _ = _run(bandred, A, w, w)
+    assert np.all(tg == 0.0)
+    assert np.array_equal(np.tril(Ag), np.tril(A))
+
+
+def test_lookahead_is_bit_identical_to_serial(bandred):
+    A = inputs.sym_normal(900, 21)
+    a1, t1, _ = _run(bandred, A, 64, 64, lookahead=True)
+    a2, t2, _ = _run(bandred, A, 64, 64, lookahead=False)
+    assert np.array_equal(np.tril(a1), np.tril(a2))
+    assert np.array_equal(t1, t2)
+
+
+def test_known_spectrum_config(bandred, orc):
+    p = inputs.make("sy2sb_n512_w32")
+    A, w = p["A"], p["w"]
+    Ag, tg, _ = _run(bandred, A, w, p["b"])
+    err = metrics.sy2sb_errors(A, np.tril(Ag), tg, w, lam=p["lam"])
+    n = A.shape[0]
+    assert err["backward"] <= 1e-14 * n
+    assert err["orth"] <= 1e-14 * n
+    assert err["eig_err"] <= 1e-14 * n
+    assert err["band_trunc"] <= 1e-14 * n
