@@ -173,6 +173,16 @@ def main():
     run64()
     torch.cuda.synchronize()
     prof = br.bandred_profile_read()
+    # the same step without look-ahead: every kernel alone on the GPU
+    restore()
+    torch.cuda.synchronize()
+    br.bandred_profile_enable(True)
+    if is_ge:
+        br.ge2gb(A, w, b, prec="fp64")
+    else:
+        br.sy2sb(A, w, b, prec="fp64", lookahead=False)
+    torch.cuda.synchronize()
+    prof_serial = br.bandred_profile_read()
     br.bandred_profile_enable(False)
     dom = max((k for k in prof if prof[k]["flops"] > 0), key=lambda k: prof[k]["ms"])
     d = prof[dom]
@@ -183,6 +193,10 @@ def main():
     breakdown = {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
                      "tflops": (v["flops"] / (v["ms"] / 1e3) / 1e12) if v["ms"] > 0 and v["flops"] > 0 else None}
                  for k, v in prof.items() if v["launches"]}
+
+    breakdown_serial = {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
+                            "tflops": (v["flops"] / (v["ms"] / 1e3) / 1e12) if v["ms"] > 0 and v["flops"] > 0 else None}
+                        for k, v in prof_serial.items() if v["launches"]}
 
     forms = {}
     if not args.no_forms:
@@ -233,6 +247,7 @@ def main():
         "accuracy": acc,
         "roofline": roofline,
         "kernels": breakdown,
+        "kernels_serial": breakdown_serial,
         "forms": forms,
         "cpu_baseline": cpu,
     }

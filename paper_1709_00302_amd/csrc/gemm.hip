@@ -24,9 +24,15 @@
 
 namespace br {
 
-// MFMA 16x16 output layout: lane l holds rows 4*(l/16) + e, e = 0..3, of
-// column l % 16.  Inputs: lane l supplies A(l % 16, l / 16) and B(l / 16, l % 16).
-__device__ __forceinline__ int mfma_row(int lane, int e) { return 4 * (lane >> 4) + e; }
+// MFMA 16x16x4 operand layout: lane l supplies A(l % 16, l / 16) and
+// B(l / 16, l % 16); the result D(i, j) sits in lane j + 16 * f(i), element g(i):
+//   v_mfma_f64_16x16x4_f64: lane l, element e holds row (l / 16) + 4 e
+//   v_mfma_f32_16x16x4_f32: lane l, element e holds row 4 (l / 16) + e
+// (both measured on gfx950), column l % 16 in both cases.
+template <int PREC>
+__device__ __forceinline__ int mfma_row(int lane, int e) {
+  return (PREC == P_F64) ? (lane >> 4) + 4 * e : 4 * (lane >> 4) + e;
+}
 __device__ __forceinline__ int mfma_col(int lane) { return lane & 15; }
 
 template <int PREC> struct Stage;
@@ -235,13 +241,13 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmDesc d) {
           for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
             for (int fn = 0; fn < FN; ++fn)
-              acc64[fm][fn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[fm], b[fn], acc64[fm][fn], 0, 0, 0);
+              acc64[fm][fn] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[fn], a[fm], acc64[fm][fn], 0, 0, 0);
         } else if constexpr (PREC == P_F32) {
 #pragma unroll
           for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
             for (int fn = 0; fn < FN; ++fn)
-              acc32[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[fm], b[fn], acc32[fm][fn], 0, 0, 0);
+              acc32[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[fn], a[fm], acc32[fm][fn], 0, 0, 0);
         } else {
           float al[FM], bl[FN];
 #pragma unroll
@@ -252,9 +258,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmDesc d) {
           for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
             for (int fn = 0; fn < FN; ++fn) {
-              acc32[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[fm], b[fn], acc32[fm][fn], 0, 0, 0);
-              accx[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[fm], bl[fn], accx[fm][fn], 0, 0, 0);
-              accx[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x4f32(al[fm], b[fn], accx[fm][fn], 0, 0, 0);
+              acc32[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[fn], a[fm], acc32[fm][fn], 0, 0, 0);
+              accx[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x4f32(bl[fn], a[fm], accx[fm][fn], 0, 0, 0);
+              accx[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[fn], al[fm], accx[fm][fn], 0, 0, 0);
             }
         }
       }
@@ -294,10 +300,13 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmDesc d) {
   for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
     for (int fn = 0; fn < FN; ++fn) {
-      const int col = j0 + wn * (BN / 2) + fn * 16 + mfma_col(lane);
+      // the MFMA computed the transposed block (B^T A^T): its row index is
+      // C's column, its column index (lane % 16) is C's row, so 16 adjacent
+      // lanes touch 16 adjacent rows of one column (128 contiguous bytes)
+      const int row = i0 + wm * (BM / 2) + fm * 16 + mfma_col(lane);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int row = i0 + wm * (BM / 2) + fm * 16 + mfma_row(lane, e);
+        const int col = j0 + wn * (BN / 2) + fn * 16 + mfma_row<PREC>(lane, e);
         if (row >= d.M || col >= Nlim) continue;
         const double v = acc64[fm][fn][e];
         if (EPI == E_AXPBY) {
