@@ -71,11 +71,17 @@ def cpu_baseline(p, A_dev):
     orc = oracle.get()
     n, w = p["n"], p["w"]
     A = A_dev.cpu().numpy()
+    # per-column cost from two short runs (the oracle's full-matrix copy in
+    # and out is a fixed cost), then a sample of about 20 s
     t0 = time.perf_counter()
-    orc.sy2sb(A, w, ncols=4)
-    t4 = time.perf_counter() - t0
-    per_col = max(t4 / 4.0, 1e-3)
-    k = int(max(4, min(n - w - 1, 15.0 / per_col)))
+    orc.sy2sb(A, w, ncols=2)
+    t2 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    orc.sy2sb(A, w, ncols=10)
+    t10 = time.perf_counter() - t0
+    per_col = max((t10 - t2) / 8.0, 1e-4)
+    fixed = max(t2 - 2.0 * per_col, 0.0)
+    k = int(max(10, min(n - w - 1, (20.0 - fixed) / per_col)))
     t0 = time.perf_counter()
     orc.sy2sb(A, w, ncols=k)
     dt = time.perf_counter() - t0

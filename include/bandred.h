@@ -62,8 +62,11 @@ typedef struct {
   int lookahead;      /* 1 (default): factor the next panel on a second stream while
                          the rest of the trailing matrix is updated (Sec. 2.2);
                          0: one stream, strictly sequential (debug / comparison) */
-  int panel_rows;     /* rows of the panel held per workgroup; 0 = automatic */
-  int reserved[6];    /* must be zero */
+  int panel_rows;     /* rows per workgroup of the per-column panel kernel; 0 = automatic */
+  int panel_method;   /* 0 (default) or 2: CholeskyQR2 + Householder reconstruction, with the
+                         per-column kernel as fallback for rank-deficient panels;
+                         1: per-column Householder kernel only */
+  int reserved[5];    /* must be zero */
 } bandred_opts_t;
 
 /* Symmetric A (n x n) to symmetric band form, bandwidth w, block size b

@@ -35,7 +35,7 @@ class BandredError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("lookahead", ctypes.c_int), ("panel_rows", ctypes.c_int),
-                ("reserved", ctypes.c_int * 6)]
+                ("panel_method", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
 
 
 _i64 = ctypes.c_int64
@@ -165,7 +165,7 @@ def _stream_handle(stream):
 
 
 def sy2sb(A, w: int, b: int | None = None, prec="fp64", lookahead: bool = True,
-          panel_rows: int = 0, stream=None, tau=None):
+          panel_rows: int = 0, panel_method: int = 0, stream=None, tau=None):
     """Reduce the symmetric column-major CUDA tensor ``A`` (lower triangle) to
     band width ``w`` in place; returns tau (device tensor)."""
     import torch
@@ -176,13 +176,14 @@ def sy2sb(A, w: int, b: int | None = None, prec="fp64", lookahead: bool = True,
     if tau is None:
         tau = torch.zeros(max(n - w, 1), dtype=torch.float64, device=A.device)
     p = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
-    o = Opts(1 if lookahead else 0, int(panel_rows))
+    o = Opts(1 if lookahead else 0, int(panel_rows), int(panel_method))
     rc = bandred_sy2sb_ex(n, w, b, A.data_ptr(), lda, tau.data_ptr(), p, o, _stream_handle(stream))
     _check("bandred_sy2sb_ex", rc)
     return tau[: max(n - w, 0)]
 
 
-def ge2gb(A, w: int, b: int | None = None, prec="fp64", panel_rows: int = 0, stream=None):
+def ge2gb(A, w: int, b: int | None = None, prec="fp64", panel_rows: int = 0,
+          panel_method: int = 0, stream=None):
     """Reduce the column-major CUDA tensor ``A`` (m >= n) to upper
     triangular-band width ``w`` in place; returns (tauq, taup)."""
     import torch
@@ -193,7 +194,7 @@ def ge2gb(A, w: int, b: int | None = None, prec="fp64", panel_rows: int = 0, str
     tauq = torch.zeros(max(n, 1), dtype=torch.float64, device=A.device)
     taup = torch.zeros(max(n, 1), dtype=torch.float64, device=A.device)
     p = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
-    o = Opts(1, int(panel_rows))
+    o = Opts(1, int(panel_rows), int(panel_method))
     rc = bandred_ge2gb_ex(m, n, w, b, A.data_ptr(), lda, tauq.data_ptr(), taup.data_ptr(), p, o,
                           _stream_handle(stream))
     _check("bandred_ge2gb_ex", rc)

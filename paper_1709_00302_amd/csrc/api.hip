@@ -3,23 +3,24 @@
 // SY2SB driver (Sec. 2.1; look-ahead Variant V2 of Sec. 2.2 when 2b > w and
 // the V1 partition when 2b <= w).  Per panel c (width pb, r = c + w,
 // j = n - r):
-//   1. panel QR of A0 = A[r:n, c:c+pb]  -> V (explicit), tau, in-place R/v
-//      (eq. updateA0)
-//   2. S = V^T V, T = larft(S, tau)      (compact WY, Q = I - V T V^T)
-//   3. A1 -= V T^T (V^T A1) on the w-pb in-band columns right of the panel
-//      (eq. updateA1; empty when b = w)
-//   4. P = A2 V (SYMM), X = P T          (eq. updateA2symm with W_paper = -V T)
-//   5. M = T^T (V^T X), W = X - 1/2 V M  (eqs. updateA2gemm1/gemm2, X3 = -W)
+//   1. panel QR of A0 = A[r:n, c:c+pb] -> V (explicit), tau, T, in-place R/v
+//      (eq. updateA0; CholeskyQR2 + Householder reconstruction, recon.hip)
+//   2. Wt = V T                          (the paper's W = -Wt, Sec. 4.1)
+//   3. A1 -= V T^T (V^T A1) = V (Wt^T A1) on the w-pb in-band columns right
+//      of the panel (eq. updateA1; empty when b = w)
+//   4. X = A2 Wt (SYMM)                  (eq. updateA2symm)
+//   5. M = Wt^T X, W = X - 1/2 V M       (eqs. updateA2gemm1/gemm2, X3 = -W)
 //   6. A2 -= W V^T + V W^T (SYR2K, lower triangle; eq. updateA2syr2k)
-// With look-ahead, step 6 is split: first the columns of A2 that belong to the
-// next panel (A2^L), then -- while the next panel is factored on a second
-// stream -- the rest (A2^R).
+// Look-ahead (Sec. 2.2) factors the next panel (steps 1-2) on a second stream:
+// Variant V1 (the next panel lies in A1, 2b <= w) forks right after step 3;
+// Variant V2 (2b > w) first applies step 6 to the columns of A2 that belong to
+// the next panel (A2^L), forks, and applies the rest (A2^R) meanwhile.
 //
 // GE2GB driver (Sec. 3.1, triangular-band form, b <= w).  Per block c:
-//   1. left QR of A[c:m, c:c+pb]                (eq. updateB)
-//   2. E = A[c:m, c+pb:n]: E -= V T^T (V^T E)    (eq. updateCD)
-//   3. right LQ of A[c:c+pr, c+w:n]             (eq. updateC)
-//   4. D = A[c+pr:m, c+w:n]: D -= (D U) T U^T    (eq. updateD)
+//   1. left QR of A[c:m, c:c+pb], Wtq = V Tq      (eq. updateB)
+//   2. E = A[c:m, c+pb:n]: E -= V (Wtq^T E)        (eq. updateCD)
+//   3. right LQ of A[c:c+pr, c+w:n], Wtp = U Tp   (eq. updateC)
+//   4. D = A[c+pr:m, c+w:n]: D -= (D Wtp) U^T      (eq. updateD)
 #include <mutex>
 #include <vector>
 #include <cstdio>
@@ -38,9 +39,10 @@ int hip_fail(hipError_t e, const char *what) {
 // ---------------------------------------------------------------------------
 // profiling (optional): events around every launch
 // ---------------------------------------------------------------------------
-enum Cls { C_PANEL = 0, C_LARFT, C_SYMM, C_SYR2K, C_GEMM_SMALL, C_REDUCE, C_GEMM_UPD, C_OTHER, C_NCLS };
-static const char *kClsNames[C_NCLS] = {"panel_qr", "larft", "symm", "syr2k",
-                                        "gemm_small", "reduce", "gemm_update", "other"};
+enum Cls { C_PANEL = 0, C_LARFT, C_SYMM, C_SYR2K, C_GEMM_SMALL, C_REDUCE, C_GEMM_UPD,
+           C_PANEL_SMALL, C_OTHER, C_NCLS };
+static const char *kClsNames[C_NCLS] = {"panel_qr", "larft", "symm", "syr2k", "gemm_small",
+                                        "reduce", "gemm_update", "panel_small", "other"};
 struct ProfRec {
   int cls;
   double flops;
@@ -169,7 +171,8 @@ struct Ctx {
 // C(M x N) = alpha op(A) op(B) + beta C, split over k when that fills the chip.
 static int gemm(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int K,
                 const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
-                int64_t ldc, double alpha, double beta, hipStream_t s) {
+                int64_t ldc, double alpha, double beta, hipStream_t s,
+                const int *gate = nullptr, int gate_val = 0) {
   if (M <= 0 || N <= 0) return 0;
   if (K <= 0) {
     if (beta == 1.0) return 0;
@@ -179,6 +182,7 @@ static int gemm(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int 
   d.M = M; d.N = N; d.K = K;
   d.A = A; d.lda = lda; d.B = B; d.ldb = ldb; d.C = C; d.ldc = ldc;
   d.alpha = alpha; d.beta = beta;
+  d.gate = gate; d.gate_val = gate_val;
   const int bm = (M <= 64 && N <= 64) ? 64 : 128;
   const int tiles = ((M + bm - 1) / bm) * ((N + bm - 1) / bm);
   const int target = 2 * cx.st->num_cu;
@@ -205,7 +209,7 @@ static int gemm(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int 
     if (rc) return rc;
   }
   ProfScope ps(C_REDUCE, 0.0, s);
-  return launch_reduce_partials(cx.part, ks, M, N, alpha, C, ldc, beta, s);
+  return launch_reduce_partials(cx.part, ks, M, N, alpha, C, ldc, beta, s, gate, gate_val);
 }
 
 // A2(lower, columns [c0, c1)) -= W V^T + V W^T with WV = [W | V] (j x 2pb).
@@ -225,9 +229,32 @@ static int syr2k(Ctx &cx, int prec, int j, int pb, const double *WV, int64_t ldw
   return launch_gemm(A_N, B_TROT, E_SYR2K, prec, d, 1, s);
 }
 
-static int panel(Ctx &cx, bool rowmajor, double *P, int64_t ldp, int m, int nb, double *V,
-                 int64_t ldv, double *tau, double *part2, double *piv, unsigned *counter,
-                 int panel_rows, hipStream_t s) {
+// Scratch of one panel factorisation.
+struct PanelWs {
+  double *G, *G2, *R1, *R1i, *R2, *R2i, *Qtop, *Ui, *M, *Rh0, *S, *sgn, *Q1;
+  double *part2, *piv;
+  static size_t bytes(int mmax, int b) {
+    return 256 * 16 + 8 * ((size_t)11 * b * b + (size_t)b + (size_t)mmax * b +
+                           (size_t)2 * 256 * kNbMax + (size_t)kNbMax * kNbMax);
+  }
+  void carve(Arena &ar, int mmax, int b) {
+    const size_t bb = (size_t)b * b;
+    G = ar.take<double>(bb); G2 = ar.take<double>(bb);
+    R1 = ar.take<double>(bb); R1i = ar.take<double>(bb);
+    R2 = ar.take<double>(bb); R2i = ar.take<double>(bb);
+    Qtop = ar.take<double>(bb); Ui = ar.take<double>(bb);
+    M = ar.take<double>(bb); Rh0 = ar.take<double>(bb); S = ar.take<double>(bb);
+    sgn = ar.take<double>(b);
+    Q1 = ar.take<double>((size_t)mmax * b);
+    part2 = ar.take<double>((size_t)2 * 256 * kNbMax);
+    piv = ar.take<double>((size_t)kNbMax * kNbMax);
+  }
+};
+
+// The per-column kernel (exact Householder, one grid barrier per column).
+static int panel_columns(Ctx &cx, bool rowmajor, double *P, int64_t ldp, int m, int nb, double *V,
+                         int64_t ldv, double *tau, PanelWs &pw, unsigned *counter, int panel_rows,
+                         const int *gate, int gate_val, hipStream_t s) {
   DevState &st = *cx.st;
   const int LDW = (nb & 1) ? nb : nb + 1;
   const int rmax = (150 * 1024) / (LDW * 8);
@@ -241,11 +268,94 @@ static int panel(Ctx &cx, bool rowmajor, double *P, int64_t ldp, int m, int nb, 
   PanelDesc d{};
   d.P = P; d.ldp = ldp; d.m = m; d.nb = nb; d.R = R;
   d.V = V; d.ldv = ldv; d.tau = tau;
-  d.part = part2; d.piv = piv; d.counter = counter;
+  d.part = pw.part2; d.piv = pw.piv; d.counter = counter;
   d.status = st.flags; d.abort_flag = st.flags + 1;
   d.timeout_ticks = st.timeout_ticks;
+  d.gate = gate; d.gate_val = gate_val;
   ProfScope ps(C_PANEL, 2.0 * (double)m * nb * nb, s);
   return launch_panel(rowmajor, d, nwg, s);
+}
+
+// Factor the m x nb panel P (column panel, or row panel when rowmajor):
+// in-place R / v storage, explicit V (m x nb, ld ldv), tau and T (nb x nb).
+//   method 1: per-column kernel + S = V^T V + T recurrence.
+//   method 0/2: CholeskyQR2 + Householder reconstruction; if the first
+//   Cholesky flags the panel as rank deficient, the per-column path runs
+//   instead (all kernels are gated on the device flag, no host round trip).
+static int panel_factor(Ctx &cx, bool rowmajor, double *P, int64_t ldp, int m, int nb, double *V,
+                        int64_t ldv, double *tau, double *T, int ldt, PanelWs &pw,
+                        unsigned *counter, int *flag, int method, int panel_rows, hipStream_t s) {
+  int rc;
+  // a square panel's last column has no rows below the diagonal (tau = 0 by
+  // the Householder convention): factor it column by column
+  if (m <= nb) method = 1;
+  if (method == 1) {
+    rc = panel_columns(cx, rowmajor, P, ldp, m, nb, V, ldv, tau, pw, counter, panel_rows, nullptr,
+                       0, s);
+    if (rc) return rc;
+    rc = gemm(cx, C_GEMM_SMALL, A_T, B_N, P_F64, nb, nb, m, V, ldv, V, ldv, pw.S, nb, 1.0, 0.0, s);
+    if (rc) return rc;
+    ProfScope p2(C_LARFT, 0.0, s);
+    return launch_larft(pw.S, nb, tau, nb, T, ldt, s);
+  }
+  const double flops = 2.0 * (double)m * nb * nb;
+  rc = launch_lower_nonzero(P, ldp, rowmajor ? 1 : 0, m, nb, flag + 1, s);
+  if (rc) return rc;
+  // G = P^T P ; R1 = chol(G), R1^-1
+  rc = gemm(cx, C_PANEL, rowmajor ? A_N : A_T, rowmajor ? B_T : B_N, P_F64, nb, nb, m, P, ldp, P,
+            ldp, pw.G, nb, 1.0, 0.0, s);
+  if (rc) return rc;
+  {
+    ProfScope p2(C_PANEL_SMALL, 0.0, s);
+    rc = launch_chol_inv(pw.G, nb, nb, 1e-10, pw.R1, pw.R1i, flag, 1, s);
+    if (rc) return rc;
+  }
+  // Q1 = P R1^-1 ; G2 = Q1^T Q1 ; R2 = chol(G2), R2^-1
+  rc = gemm(cx, C_PANEL, rowmajor ? A_T : A_N, B_N, P_F64, m, nb, nb, P, ldp, pw.R1i, nb, pw.Q1,
+            m, 1.0, 0.0, s, flag, 0);
+  if (rc) return rc;
+  rc = gemm(cx, C_PANEL, A_T, B_N, P_F64, nb, nb, m, pw.Q1, m, pw.Q1, m, pw.G2, nb, 1.0, 0.0, s,
+            flag, 0);
+  if (rc) return rc;
+  {
+    ProfScope p2(C_PANEL_SMALL, 0.0, s);
+    rc = launch_chol_inv(pw.G2, nb, nb, 1e-6, pw.R2, pw.R2i, flag, 0, s);
+    if (rc) return rc;
+  }
+  // Qtop = Q1(0:nb, :) R2^-1 ; LU with signs, T, U^-1
+  rc = gemm(cx, C_PANEL, A_N, B_N, P_F64, nb, nb, nb, pw.Q1, m, pw.R2i, nb, pw.Qtop, nb, 1.0, 0.0,
+            s, flag, 0);
+  if (rc) return rc;
+  {
+    ProfScope p2(C_PANEL_SMALL, 0.0, s);
+    rc = launch_recon(pw.Qtop, nb, nb, V, ldv, T, ldt, tau, pw.Ui, pw.sgn, flag, s);
+    if (rc) return rc;
+  }
+  // M = R2^-1 U^-1 ; Rh0 = R2 R1 ; V(nb:m, :) = Q1(nb:m, :) M ; write in place
+  rc = gemm(cx, C_PANEL, A_N, B_N, P_F64, nb, nb, nb, pw.R2i, nb, pw.Ui, nb, pw.M, nb, 1.0, 0.0, s,
+            flag, 0);
+  if (rc) return rc;
+  rc = gemm(cx, C_PANEL, A_N, B_N, P_F64, nb, nb, nb, pw.R2, nb, pw.R1, nb, pw.Rh0, nb, 1.0, 0.0,
+            s, flag, 0);
+  if (rc) return rc;
+  if (m > nb) {
+    rc = gemm(cx, C_PANEL, A_N, B_N, P_F64, m - nb, nb, nb, pw.Q1 + nb, m, pw.M, nb, V + nb, ldv,
+              1.0, 0.0, s, flag, 0);
+    if (rc) return rc;
+  }
+  {
+    ProfScope p2(C_PANEL_SMALL, flops, s);
+    rc = launch_panel_finalize(P, ldp, rowmajor ? 1 : 0, m, nb, V, ldv, pw.Rh0, pw.sgn, flag, s);
+    if (rc) return rc;
+  }
+  // fallback for flagged (rank-deficient) panels
+  rc = panel_columns(cx, rowmajor, P, ldp, m, nb, V, ldv, tau, pw, counter, panel_rows, flag, 1, s);
+  if (rc) return rc;
+  rc = gemm(cx, C_GEMM_SMALL, A_T, B_N, P_F64, nb, nb, m, V, ldv, V, ldv, pw.S, nb, 1.0, 0.0, s,
+            flag, 1);
+  if (rc) return rc;
+  ProfScope p3(C_LARFT, 0.0, s);
+  return launch_larft(pw.S, nb, tau, nb, T, ldt, s, flag, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -254,132 +364,122 @@ static int panel(Ctx &cx, bool rowmajor, double *P, int64_t ldp, int m, int nb, 
 static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t lda, double *tau,
                       int prec, const bandred_opts_t *opts, hipStream_t s) {
   if (n64 <= w64 + 1) {
-    if (n64 > w64) {
-      // one trivial reflector of length 1
-      return launch_fill(tau, n64 - w64, 0.0, s);
-    }
+    if (n64 > w64) return launch_fill(tau, n64 - w64, 0.0, s);  // one trivial reflector
     return 0;
   }
   if (n64 > (int64_t)1 << 30) return BANDRED_ERR_UNSUPPORTED;
   const int n = (int)n64, w = (int)w64, b = (int)b64;
   const int lookahead = opts ? opts->lookahead : 1;
   const int panel_rows = opts ? opts->panel_rows : 0;
+  const int method = opts ? opts->panel_method : 0;
   DevState *st = nullptr;
   int rc = dev_state(&st);
   if (rc) return rc;
 
-  const int nref = n - w - 1;               // reflector columns 0 .. n-w-2
+  const int nref = n - w - 1;  // reflector columns 0 .. n-w-2
   const int npan = (nref + b - 1) / b;
-  const int jmax = n - w;                    // rows of the first panel
-  const size_t part_cap = std::max<size_t>((size_t)8 * jmax * b, (size_t)256 * b * b);
+  const int jmax = n - w;      // rows of the first panel
+  const size_t part_main = std::max<size_t>((size_t)8 * jmax * b, (size_t)256 * b * b);
+  const size_t part_pan = (size_t)(jmax / 256 + 2) * b * b;
   size_t need = 0;
-  need += 2 * round_up((size_t)jmax * 2 * b * 8, 256);        // WV[2]
-  need += round_up((size_t)jmax * b * 8, 256);                // P
-  need += round_up(part_cap * 8, 256);                        // split-k partials
-  need += 6 * round_up((size_t)b * std::max(b, w) * 8, 256);  // S T Y M Z Z2
-  need += round_up((size_t)2 * 256 * kNbMax * 8, 256);        // panel partials
-  need += round_up((size_t)kNbMax * kNbMax * 8, 256);         // pivot rows
-  need += round_up((size_t)(npan + 1) * 4, 256);              // counters
-  need += 4096;
+  need += 2 * round_up((size_t)jmax * 2 * b * 8, 256);   // WV[2] = [W | V]
+  need += 2 * round_up((size_t)jmax * b * 8, 256);       // Wt[2] = V T
+  need += round_up(part_main * 8, 256) + round_up(part_pan * 8, 256);
+  need += 4 * round_up((size_t)b * std::max(b, w) * 8, 256);  // T[2], M, Z
+  need += PanelWs::bytes(jmax, b);
+  need += 3 * round_up((size_t)(npan + 1) * 4, 256);     // counters, flags (2 per panel)
+  need += 8192;
   std::lock_guard<std::mutex> lk(g_mu);
   rc = ws_reserve(*st, need);
   if (rc) return rc;
   Arena ar(st->base);
   double *WVbuf[2] = {ar.take<double>((size_t)jmax * 2 * b), ar.take<double>((size_t)jmax * 2 * b)};
-  double *Pb = ar.take<double>((size_t)jmax * b);
-  double *part = ar.take<double>(part_cap);
+  double *Wtb[2] = {ar.take<double>((size_t)jmax * b), ar.take<double>((size_t)jmax * b)};
+  double *partm = ar.take<double>(part_main);
+  double *partp = ar.take<double>(part_pan);
   const size_t sq = (size_t)b * std::max(b, w);
-  double *Sb = ar.take<double>(sq), *Tb[2] = {ar.take<double>(sq), ar.take<double>(sq)};
-  double *Yb = ar.take<double>(sq), *Mb = ar.take<double>(sq), *Zb = ar.take<double>(sq);
-  double *Z2b = ar.take<double>(sq);
-  double *part2 = ar.take<double>((size_t)2 * 256 * kNbMax);
-  double *piv = ar.take<double>((size_t)kNbMax * kNbMax);
+  double *Tb[2] = {ar.take<double>(sq), ar.take<double>(sq)};
+  double *Mb = ar.take<double>(sq), *Zb = ar.take<double>(sq);
+  PanelWs pw;
+  pw.carve(ar, jmax, b);
   unsigned *counters = ar.take<unsigned>(npan + 1);
+  int *pflags = ar.take<int>(2 * (npan + 1));
 
-  Ctx cx{st, s, part, part_cap};
+  Ctx cxm{st, s, partm, part_main};
   hipStream_t ps = lookahead ? st->aux : s;  // panel stream
+  Ctx cxp{st, ps, partp, part_pan};
 
-  // order after the previous call, reset flags and counters
   BR_HIP_CHECK(hipStreamWaitEvent(s, st->done, 0));
   rc = launch_fill_u32(counters, npan + 1, 0u, s); if (rc) return rc;
+  rc = launch_fill_u32((unsigned *)pflags, 2 * (npan + 1), 0u, s); if (rc) return rc;
   rc = launch_fill_u32((unsigned *)st->flags, 2, 0u, s); if (rc) return rc;
   rc = launch_fill(tau, n - w, 0.0, s); if (rc) return rc;
 
-  // prologue: panel 0 on the main stream
-  {
-    const int pb = std::min(b, nref);
-    const int r = w, j = n - r;
-    double *V = WVbuf[0] + (int64_t)pb * j;
-    rc = panel(cx, false, A + r, lda, j, pb, V, j, tau, part2, piv, counters, panel_rows, s);
-    if (rc) return rc;
-    rc = gemm(cx, C_GEMM_SMALL, A_T, B_N, P_F64, pb, pb, j, V, j, V, j, Sb, pb, 1.0, 0.0, s);
-    if (rc) return rc;
-    { ProfScope p2(C_LARFT, 0.0, s); rc = launch_larft(Sb, pb, tau, pb, Tb[0], pb, s); }
-    if (rc) return rc;
-  }
+  // panel `it` (columns c .. c+pb-1) and its Wt = V T, on stream q
+  auto factor = [&](int it, Ctx &cx, hipStream_t q) -> int {
+    const int c = it * b, pb = std::min(b, nref - c), r = c + w, j = n - r;
+    double *V = WVbuf[it & 1] + (int64_t)pb * j;
+    int e = panel_factor(cx, false, A + r + (int64_t)c * lda, lda, j, pb, V, j, tau + c,
+                         Tb[it & 1], pb, pw, counters + it, pflags + 2 * it, method, panel_rows, q);
+    if (e) return e;
+    return gemm(cx, C_GEMM_SMALL, A_N, B_N, P_F64, j, pb, pb, V, j, Tb[it & 1], pb, Wtb[it & 1], j,
+                1.0, 0.0, q);
+  };
+
+  rc = factor(0, cxm, s);
+  if (rc) return rc;
 
   for (int it = 0, c = 0; c < nref; ++it, c += b) {
     const int pb = std::min(b, nref - c);
     const int r = c + w, j = n - r;
     double *WV = WVbuf[it & 1];
     double *W = WV, *V = WV + (int64_t)pb * j;
-    double *T = Tb[it & 1];
+    double *Wt = Wtb[it & 1];
     double *A2 = A + r + (int64_t)r * lda;
 
-    // next panel geometry
     const int cn = c + b;
     const bool has_next = cn < nref;
     const int pbn = has_next ? std::min(b, nref - cn) : 0;
-    const int rn = cn + w, jn = n - rn;
-    // columns of the next panel inside A1 ([cn, r)) and inside A2 ([r, cn+pbn))
-    const int nxt_a1_lo = cn, nxt_a1_hi = std::min(cn + pbn, r);
-    const int a2L = has_next ? std::max(0, cn + pbn - r) : 0;  // A2 columns the next panel needs
+    const int a2L = has_next ? std::max(0, cn + pbn - r) : 0;  // A2 columns of the next panel
 
-    // (3) left update of A1 = A[r:n, c+pb : r]
-    const int a1w = w - pb;
-    if (a1w > 0) {
-      double *A1 = A + r + (int64_t)(c + pb) * lda;
-      rc = gemm(cx, C_GEMM_SMALL, A_T, B_N, P_F64, pb, a1w, j, V, j, A1, lda, Zb, pb, 1.0, 0.0, s);
-      if (rc) return rc;
-      rc = gemm(cx, C_GEMM_SMALL, A_T, B_N, P_F64, pb, a1w, pb, T, pb, Zb, pb, Z2b, pb, 1.0, 0.0, s);
-      if (rc) return rc;
-      rc = gemm(cx, C_GEMM_UPD, A_N, B_N, prec, j, a1w, pb, V, j, Z2b, pb, A1, lda, -1.0, 1.0, s);
-      if (rc) return rc;
-    }
-    (void)nxt_a1_lo; (void)nxt_a1_hi;
-    // (4) P = A2 V ; X = P T  (X stored in W's slot)
-    rc = gemm(cx, C_SYMM, A_SYM, B_N, prec, j, pb, j, A2, lda, V, j, Pb, j, 1.0, 0.0, s);
-    if (rc) return rc;
-    rc = gemm(cx, C_GEMM_SMALL, A_N, B_N, P_F64, j, pb, pb, Pb, j, T, pb, W, j, 1.0, 0.0, s);
-    if (rc) return rc;
-    // (5) Y = V^T X ; M = T^T Y ; W = X - 1/2 V M
-    rc = gemm(cx, C_GEMM_SMALL, A_T, B_N, P_F64, pb, pb, j, V, j, W, j, Yb, pb, 1.0, 0.0, s);
-    if (rc) return rc;
-    rc = gemm(cx, C_GEMM_SMALL, A_T, B_N, P_F64, pb, pb, pb, T, pb, Yb, pb, Mb, pb, 1.0, 0.0, s);
-    if (rc) return rc;
-    rc = gemm(cx, C_GEMM_SMALL, A_N, B_N, P_F64, j, pb, pb, V, j, Mb, pb, W, j, -0.5, 1.0, s);
-    if (rc) return rc;
-    // (6) SYR2K: A2^L first, then the next panel (look-ahead) overlapped with A2^R
-    rc = syr2k(cx, prec, j, pb, WV, j, A2, lda, 0, a2L, s);
-    if (rc) return rc;
-    if (has_next) {
+    auto fork_next = [&]() -> int {
+      if (!has_next) return 0;
       if (ps != s) {
         BR_HIP_CHECK(hipEventRecord(st->ev_a, s));
         BR_HIP_CHECK(hipStreamWaitEvent(ps, st->ev_a, 0));
       }
-      double *WVn = WVbuf[(it + 1) & 1];
-      double *Vn = WVn + (int64_t)pbn * jn;
-      double *Tn = Tb[(it + 1) & 1];
-      rc = panel(cx, false, A + rn + (int64_t)cn * lda, lda, jn, pbn, Vn, jn, tau + cn, part2, piv,
-                 counters + it + 1, panel_rows, ps);
+      return factor(it + 1, cxp, ps);
+    };
+
+    // (3) A1 = A[r:n, c+pb : r] -= V T^T (V^T A1) = V (Wt^T A1)   (eq. updateA1)
+    const int a1w = w - pb;
+    if (a1w > 0) {
+      double *A1 = A + r + (int64_t)(c + pb) * lda;
+      rc = gemm(cxm, C_GEMM_SMALL, A_T, B_N, P_F64, pb, a1w, j, Wt, j, A1, lda, Zb, pb, 1.0, 0.0, s);
       if (rc) return rc;
-      rc = gemm(cx, C_GEMM_SMALL, A_T, B_N, P_F64, pbn, pbn, jn, Vn, jn, Vn, jn, Sb, pbn, 1.0, 0.0,
-                ps);
-      if (rc) return rc;
-      { ProfScope p2(C_LARFT, 0.0, ps); rc = launch_larft(Sb, pbn, tau + cn, pbn, Tn, pbn, ps); }
+      rc = gemm(cxm, C_GEMM_UPD, A_N, B_N, prec, j, a1w, pb, V, j, Zb, pb, A1, lda, -1.0, 1.0, s);
       if (rc) return rc;
     }
-    rc = syr2k(cx, prec, j, pb, WV, j, A2, lda, a2L, j, s);
+    // Variant V1 (the next panel lies inside A1): fork right away
+    if (a2L == 0) {
+      rc = fork_next();
+      if (rc) return rc;
+    }
+    // (4) X = A2 Wt (SYMM) into W's slot; M = Wt^T X; W = X - 1/2 V M
+    rc = gemm(cxm, C_SYMM, A_SYM, B_N, prec, j, pb, j, A2, lda, Wt, j, W, j, 1.0, 0.0, s);
+    if (rc) return rc;
+    rc = gemm(cxm, C_GEMM_SMALL, A_T, B_N, P_F64, pb, pb, j, Wt, j, W, j, Mb, pb, 1.0, 0.0, s);
+    if (rc) return rc;
+    rc = gemm(cxm, C_GEMM_SMALL, A_N, B_N, P_F64, j, pb, pb, V, j, Mb, pb, W, j, -0.5, 1.0, s);
+    if (rc) return rc;
+    // (6) SYR2K: the next panel's columns A2^L first, then fork (Variant V2)
+    rc = syr2k(cxm, prec, j, pb, WV, j, A2, lda, 0, a2L, s);
+    if (rc) return rc;
+    if (a2L > 0) {
+      rc = fork_next();
+      if (rc) return rc;
+    }
+    rc = syr2k(cxm, prec, j, pb, WV, j, A2, lda, a2L, j, s);
     if (rc) return rc;
     if (has_next && ps != s) {
       BR_HIP_CHECK(hipEventRecord(st->ev_b, ps));
@@ -400,40 +500,41 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
   if (m64 > (int64_t)1 << 30) return BANDRED_ERR_UNSUPPORTED;
   const int m = (int)m64, n = (int)n64, w = (int)w64, b = (int)b64;
   const int panel_rows = opts ? opts->panel_rows : 0;
+  const int method = opts ? opts->panel_method : 0;
   DevState *st = nullptr;
   int rc = dev_state(&st);
   if (rc) return rc;
   const int npan = (n + b - 1) / b;
   const size_t part_cap = std::max<size_t>((size_t)8 * m * b, (size_t)256 * b * b);
   size_t need = 0;
-  need += round_up((size_t)m * b * 8, 256);           // V (left)
-  need += round_up((size_t)n * b * 8, 256);           // U (right)
-  need += round_up((size_t)b * n * 8, 256) * 2;       // Z, Z2 (b x n)
-  need += round_up((size_t)m * b * 8, 256) * 2;       // X, X2 (m x b)
+  need += 2 * round_up((size_t)m * b * 8, 256);       // Vq, Wtq
+  need += 2 * round_up((size_t)n * b * 8, 256);       // Up, Wtp
+  need += round_up((size_t)b * n * 8, 256);           // Z (b x n)
+  need += round_up((size_t)m * b * 8, 256);           // X (m x b)
   need += round_up(part_cap * 8, 256);
-  need += 3 * round_up((size_t)b * b * 8, 256);       // S, Tq, Tp
-  need += round_up((size_t)2 * 256 * kNbMax * 8, 256);
-  need += round_up((size_t)kNbMax * kNbMax * 8, 256);
-  need += round_up((size_t)(2 * npan + 2) * 4, 256);
-  need += 4096;
+  need += 2 * round_up((size_t)b * b * 8, 256);       // Tq, Tp
+  need += PanelWs::bytes(m, b);
+  need += 3 * round_up((size_t)(2 * npan + 2) * 4, 256);
+  need += 8192;
   std::lock_guard<std::mutex> lk(g_mu);
   rc = ws_reserve(*st, need);
   if (rc) return rc;
   Arena ar(st->base);
-  double *Vq = ar.take<double>((size_t)m * b);
-  double *Up = ar.take<double>((size_t)n * b);
-  double *Zb = ar.take<double>((size_t)b * n), *Z2b = ar.take<double>((size_t)b * n);
-  double *Xb = ar.take<double>((size_t)m * b), *X2b = ar.take<double>((size_t)m * b);
+  double *Vq = ar.take<double>((size_t)m * b), *Wtq = ar.take<double>((size_t)m * b);
+  double *Up = ar.take<double>((size_t)n * b), *Wtp = ar.take<double>((size_t)n * b);
+  double *Zb = ar.take<double>((size_t)b * n);
+  double *Xb = ar.take<double>((size_t)m * b);
   double *part = ar.take<double>(part_cap);
-  double *Sb = ar.take<double>((size_t)b * b), *Tq = ar.take<double>((size_t)b * b);
-  double *Tp = ar.take<double>((size_t)b * b);
-  double *part2 = ar.take<double>((size_t)2 * 256 * kNbMax);
-  double *piv = ar.take<double>((size_t)kNbMax * kNbMax);
+  double *Tq = ar.take<double>((size_t)b * b), *Tp = ar.take<double>((size_t)b * b);
+  PanelWs pw;
+  pw.carve(ar, m, b);
   unsigned *counters = ar.take<unsigned>(2 * npan + 2);
+  int *pflags = ar.take<int>(2 * (2 * npan + 2));
   Ctx cx{st, s, part, part_cap};
 
   BR_HIP_CHECK(hipStreamWaitEvent(s, st->done, 0));
   rc = launch_fill_u32(counters, 2 * npan + 2, 0u, s); if (rc) return rc;
+  rc = launch_fill_u32((unsigned *)pflags, 2 * (2 * npan + 2), 0u, s); if (rc) return rc;
   rc = launch_fill_u32((unsigned *)st->flags, 2, 0u, s); if (rc) return rc;
   rc = launch_fill(tauq, n, 0.0, s); if (rc) return rc;
   rc = launch_fill(taup, n, 0.0, s); if (rc) return rc;
@@ -441,45 +542,37 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
   for (int it = 0, c = 0; c < n; ++it, c += b) {
     const int pb = std::min(b, n - c);
     const int i = m - c;
-    // (1) left panel QR of A[c:m, c:c+pb]
-    rc = panel(cx, false, A + c + (int64_t)c * lda, lda, i, pb, Vq, i, tauq + c, part2, piv,
-               counters + 2 * it, panel_rows, s);
+    // (1) left panel QR of A[c:m, c:c+pb]; Wtq = Vq Tq
+    rc = panel_factor(cx, false, A + c + (int64_t)c * lda, lda, i, pb, Vq, i, tauq + c, Tq, pb, pw,
+                      counters + 2 * it, pflags + 4 * it, method, panel_rows, s);
     if (rc) return rc;
-    rc = gemm(cx, C_GEMM_SMALL, A_T, B_N, P_F64, pb, pb, i, Vq, i, Vq, i, Sb, pb, 1.0, 0.0, s);
+    rc = gemm(cx, C_GEMM_SMALL, A_N, B_N, P_F64, i, pb, pb, Vq, i, Tq, pb, Wtq, i, 1.0, 0.0, s);
     if (rc) return rc;
-    { ProfScope p2(C_LARFT, 0.0, s); rc = launch_larft(Sb, pb, tauq + c, pb, Tq, pb, s); }
-    if (rc) return rc;
-    // (2) E = A[c:m, c+pb:n] -= V T^T (V^T E)
+    // (2) E = A[c:m, c+pb:n] -= Vq (Wtq^T E)
     const int ne = n - c - pb;
     if (ne > 0) {
       double *E = A + c + (int64_t)(c + pb) * lda;
-      rc = gemm(cx, C_GEMM_UPD, A_T, B_N, prec, pb, ne, i, Vq, i, E, lda, Zb, pb, 1.0, 0.0, s);
+      rc = gemm(cx, C_GEMM_UPD, A_T, B_N, prec, pb, ne, i, Wtq, i, E, lda, Zb, pb, 1.0, 0.0, s);
       if (rc) return rc;
-      rc = gemm(cx, C_GEMM_SMALL, A_T, B_N, P_F64, pb, ne, pb, Tq, pb, Zb, pb, Z2b, pb, 1.0, 0.0, s);
-      if (rc) return rc;
-      rc = gemm(cx, C_GEMM_UPD, A_N, B_N, prec, i, ne, pb, Vq, i, Z2b, pb, E, lda, -1.0, 1.0, s);
+      rc = gemm(cx, C_GEMM_UPD, A_N, B_N, prec, i, ne, pb, Vq, i, Zb, pb, E, lda, -1.0, 1.0, s);
       if (rc) return rc;
     }
-    // (3) right LQ of the rows c .. c+pr-1 that own a right reflector
+    // (3) right LQ of the rows c .. c+pr-1 that own a right reflector; Wtp = U Tp
     const int pr = std::max(0, std::min(pb, n - w - 1 - c));
     if (pr > 0) {
       const int c0 = c + w, jr = n - c0;
-      rc = panel(cx, true, A + c + (int64_t)c0 * lda, lda, jr, pr, Up, jr, taup + c, part2, piv,
-                 counters + 2 * it + 1, panel_rows, s);
+      rc = panel_factor(cx, true, A + c + (int64_t)c0 * lda, lda, jr, pr, Up, jr, taup + c, Tp, pr,
+                        pw, counters + 2 * it + 1, pflags + 4 * it + 2, method, panel_rows, s);
       if (rc) return rc;
-      rc = gemm(cx, C_GEMM_SMALL, A_T, B_N, P_F64, pr, pr, jr, Up, jr, Up, jr, Sb, pr, 1.0, 0.0, s);
+      rc = gemm(cx, C_GEMM_SMALL, A_N, B_N, P_F64, jr, pr, pr, Up, jr, Tp, pr, Wtp, jr, 1.0, 0.0, s);
       if (rc) return rc;
-      { ProfScope p2(C_LARFT, 0.0, s); rc = launch_larft(Sb, pr, taup + c, pr, Tp, pr, s); }
-      if (rc) return rc;
-      // (4) D = A[c+pr:m, c0:n]: X = D U ; X2 = X T ; D -= X2 U^T
+      // (4) D = A[c+pr:m, c0:n] -= (D Wtp) U^T
       const int md = m - c - pr;
       if (md > 0) {
         double *D = A + (c + pr) + (int64_t)c0 * lda;
-        rc = gemm(cx, C_GEMM_UPD, A_N, B_N, prec, md, pr, jr, D, lda, Up, jr, Xb, md, 1.0, 0.0, s);
+        rc = gemm(cx, C_GEMM_UPD, A_N, B_N, prec, md, pr, jr, D, lda, Wtp, jr, Xb, md, 1.0, 0.0, s);
         if (rc) return rc;
-        rc = gemm(cx, C_GEMM_SMALL, A_N, B_N, P_F64, md, pr, pr, Xb, md, Tp, pr, X2b, md, 1.0, 0.0, s);
-        if (rc) return rc;
-        rc = gemm(cx, C_GEMM_UPD, A_N, B_T, prec, md, jr, pr, X2b, md, Up, jr, D, lda, -1.0, 1.0, s);
+        rc = gemm(cx, C_GEMM_UPD, A_N, B_T, prec, md, jr, pr, Xb, md, Up, jr, D, lda, -1.0, 1.0, s);
         if (rc) return rc;
       }
     }
@@ -539,7 +632,8 @@ static int check_opts(const bandred_opts_t *o) {
   if (!o) return 0;
   if (o->lookahead != 0 && o->lookahead != 1) return 1;
   if (o->panel_rows < 0) return 1;
-  for (int i = 0; i < 6; ++i)
+  if (o->panel_method < 0 || o->panel_method > 2) return 1;
+  for (int i = 0; i < 5; ++i)
     if (o->reserved[i] != 0) return 1;
   return 0;
 }

@@ -46,6 +46,8 @@ struct GemmDesc {
   double *part;    // E_PART output: part + z*M*N, column-major ld M
   int rot;         // B_TROT rotation
   int c0, c1;      // E_SYR2K: columns [c0, c1) of C, rows >= c0
+  const int *gate; // when set, the kernel runs only if *gate == gate_val
+  int gate_val;
 };
 
 struct PanelDesc {
@@ -61,6 +63,8 @@ struct PanelDesc {
   int *status;      // set to 4 (timeout) if a wait gives up
   int *abort_flag;  // raised by the first workgroup that gives up
   long long timeout_ticks;  // bound of one wait, in s_memrealtime ticks
+  const int *gate;  // when set, the kernel runs only if *gate == gate_val
+  int gate_val;
 };
 
 }  // namespace br
@@ -78,10 +82,21 @@ int hip_fail(hipError_t e, const char *what);
 int launch_gemm(int opa, int opb, int epi, int prec, const GemmDesc &d, int ksplit,
                 hipStream_t s);
 int launch_reduce_partials(const double *part, int ksplit, int M, int N, double alpha,
-                           double *C, int64_t ldc, double beta, hipStream_t s);
+                           double *C, int64_t ldc, double beta, hipStream_t s,
+                           const int *gate = nullptr, int gate_val = 0);
 int launch_panel(bool rowmajor, const PanelDesc &d, int nwg, hipStream_t s);
 int launch_larft(const double *S, int ldS, const double *tau, int nb, double *T, int ldT,
-                 hipStream_t s);
+                 hipStream_t s, const int *gate = nullptr, int gate_val = 0);
+int launch_chol_inv(const double *G, int ldg, int b, double rel, double *R, double *Rinv, int *flag,
+                    int check_structure, hipStream_t s);
+int launch_recon(const double *Qtop, int ldq, int b, double *V, int64_t ldv, double *T, int ldt,
+                 double *tau, double *Uinv, double *sgn, const int *flag, hipStream_t s);
+int launch_lower_nonzero(const double *P, int64_t ldp, int rowmajor, int m, int b, int *count,
+                         hipStream_t s);
+int launch_panel_finalize(double *P, int64_t ldp, int rowmajor, int m, int b, const double *V,
+                          int64_t ldv, const double *Rh0, const double *sgn, const int *flag,
+                          hipStream_t s);
+constexpr int kPackedMax = kNbMax * (kNbMax + 1) / 2;
 int launch_fill(double *p, int64_t count, double v, hipStream_t s);
 int launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t s);
 int panel_lds_bytes(int R, int nb);

@@ -171,6 +171,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmDesc d) {
   __shared__ T As[2 * NP * SA];
   __shared__ T Bs[2 * NP * SB];
 
+  if (d.gate && *d.gate != d.gate_val) return;
   int i0, j0, kbeg, kend;
   if (EPI == E_SYR2K) {
     const int I = blockIdx.x, J = blockIdx.y;
@@ -295,37 +296,50 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmDesc d) {
         for (int e = 0; e < 4; ++e) acc64[fm][fn][e] = (double)acc32[fm][fn][e];
   }
 
-  // epilogue
+  // epilogue.  C is read in groups of 16 values (one fm row of blocks) that
+  // are all loaded before any is stored, so the loads overlap instead of
+  // waiting behind the stores they might alias.
+  const bool readC = (EPI == E_SYR2K) || (EPI == E_AXPBY && d.beta != 0.0);
 #pragma unroll
-  for (int fm = 0; fm < FM; ++fm)
+  for (int fm = 0; fm < FM; ++fm) {
+    // the MFMA computed the transposed block (B^T A^T): its row index is
+    // C's column, its column index (lane % 16) is C's row, so 16 adjacent
+    // lanes touch 16 adjacent rows of one column (128 contiguous bytes)
+    const int row = i0 + wm * (BM / 2) + fm * 16 + mfma_col(lane);
+    double cv[FN][4];
+    bool ok[FN][4];
 #pragma unroll
-    for (int fn = 0; fn < FN; ++fn) {
-      // the MFMA computed the transposed block (B^T A^T): its row index is
-      // C's column, its column index (lane % 16) is C's row, so 16 adjacent
-      // lanes touch 16 adjacent rows of one column (128 contiguous bytes)
-      const int row = i0 + wm * (BM / 2) + fm * 16 + mfma_col(lane);
+    for (int fn = 0; fn < FN; ++fn)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int col = j0 + wn * (BN / 2) + fn * 16 + mfma_row<PREC>(lane, e);
-        if (row >= d.M || col >= Nlim) continue;
+        bool in = (row < d.M && col < Nlim);
+        if (EPI == E_SYR2K) in = in && (row >= col);
+        ok[fn][e] = in;
+        cv[fn][e] = (readC && in) ? d.C[row + (int64_t)col * d.ldc] : 0.0;
+      }
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (!ok[fn][e]) continue;
+        const int col = j0 + wn * (BN / 2) + fn * 16 + mfma_row<PREC>(lane, e);
         const double v = acc64[fm][fn][e];
         if (EPI == E_AXPBY) {
-          double *c = d.C + row + (int64_t)col * d.ldc;
-          *c = (d.beta == 0.0) ? d.alpha * v : d.alpha * v + d.beta * (*c);
+          d.C[row + (int64_t)col * d.ldc] = readC ? d.alpha * v + d.beta * cv[fn][e] : d.alpha * v;
         } else if (EPI == E_PART) {
           d.part[(int64_t)blockIdx.z * d.M * d.N + row + (int64_t)col * d.M] = v;
         } else {
-          if (row >= col) {
-            double *c = d.C + row + (int64_t)col * d.ldc;
-            *c -= v;
-          }
+          d.C[row + (int64_t)col * d.ldc] = cv[fn][e] - v;
         }
       }
-    }
+  }
 }
 
 __global__ void k_reduce_partials(const double *part, int ksplit, int M, int N, double alpha,
-                                  double *C, int64_t ldc, double beta) {
+                                  double *C, int64_t ldc, double beta, const int *gate,
+                                  int gate_val) {
+  if (gate && *gate != gate_val) return;
   const int64_t total = (int64_t)M * N;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -379,6 +393,7 @@ static int dispatch_ops(int opa, int opb, int epi, const GemmDesc &d, int ksplit
   BR_CASE(A_T, B_N, E_AXPBY)
   BR_CASE(A_T, B_N, E_PART)
   BR_CASE(A_N, B_T, E_AXPBY)
+  BR_CASE(A_N, B_T, E_PART)
   BR_CASE(A_N, B_TROT, E_SYR2K)
 #undef BR_CASE
   return BANDRED_ERR_UNSUPPORTED;
@@ -386,7 +401,9 @@ static int dispatch_ops(int opa, int opb, int epi, const GemmDesc &d, int ksplit
 
 int launch_gemm(int opa, int opb, int epi, int prec, const GemmDesc &d, int ksplit,
                 hipStream_t s) {
-  const bool small = (d.M <= 64 && (epi == E_SYR2K ? (d.c1 - d.c0) : d.N) <= 64);
+  // 64 x 64 tiles for outputs up to 128 x 128 (the b x b products and Gram
+  // matrices), so that such products still spread over several workgroups
+  const bool small = (d.M <= 128 && (epi == E_SYR2K ? (d.c1 - d.c0) : d.N) <= 128);
   int rc;
   if (prec == P_F64) {
     rc = small ? dispatch_ops<64, 64, P_F64>(opa, opb, epi, d, ksplit, s)
@@ -403,13 +420,14 @@ int launch_gemm(int opa, int opb, int epi, int prec, const GemmDesc &d, int kspl
 }
 
 int launch_reduce_partials(const double *part, int ksplit, int M, int N, double alpha,
-                           double *C, int64_t ldc, double beta, hipStream_t s) {
+                           double *C, int64_t ldc, double beta, hipStream_t s, const int *gate,
+                           int gate_val) {
   const int64_t total = (int64_t)M * N;
   if (total <= 0) return 0;
   int blocks = (int)((total + 255) / 256);
   if (blocks > 2048) blocks = 2048;
   hipLaunchKernelGGL(k_reduce_partials, dim3(blocks), dim3(256), 0, s, part, ksplit, M, N, alpha,
-                     C, ldc, beta);
+                     C, ldc, beta, gate, gate_val);
   BR_HIP_CHECK(hipGetLastError());
   return 0;
 }

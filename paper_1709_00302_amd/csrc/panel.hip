@@ -54,6 +54,7 @@ __global__ __launch_bounds__(kThreads) void k_panel(PanelDesc d) {
   __shared__ double zv[kNbMax];
   __shared__ int go;
 
+  if (d.gate && *d.gate != d.gate_val) return;
   const int nb = d.nb;
   const int LDW = (nb & 1) ? nb : nb + 1;
   const int g = blockIdx.x, nwg = gridDim.x, tid = threadIdx.x;
@@ -86,9 +87,13 @@ __global__ __launch_bounds__(kThreads) void k_panel(PanelDesc d) {
     }
     __syncthreads();
     double *pbuf = d.part + (size_t)(i & 1) * nwg * kNbMax;
-    if (tid < kNbMax && k >= i && k < nb) {
-      pbuf[g * kNbMax + k] = red[0][k] + red[1][k];
-      if (g == 0) d.piv[i * kNbMax + k] = L[i * LDW + k];
+    if (tid < kNbMax) {
+      if (k >= i && k < nb) {
+        pbuf[g * kNbMax + k] = red[0][k] + red[1][k];
+        if (g == 0) d.piv[i * kNbMax + k] = L[i * LDW + k];
+      }
+      // make this wave's stores visible device-wide before the arrival below
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
     // (2) grid barrier
     __syncthreads();
@@ -159,7 +164,9 @@ __global__ __launch_bounds__(kThreads) void k_panel(PanelDesc d) {
 // T factor of the compact WY form (the T of Sec. 4.1's W = Y T):
 // T(i,i) = tau_i, T(0:i, i) = -tau_i T(0:i, 0:i) S(0:i, i) with S = V^T V.
 __global__ __launch_bounds__(kThreads) void k_larft(const double *S, int ldS, const double *tau,
-                                                    int nb, double *T, int ldT) {
+                                                    int nb, double *T, int ldT, const int *gate,
+                                                    int gate_val) {
+  if (gate && *gate != gate_val) return;
   constexpr int LD = kNbMax + 1;
   __shared__ double Tl[kNbMax * LD];  // column-major: Tl[m*LD + l] = T(l, m)
   __shared__ double s[kNbMax];
@@ -213,8 +220,9 @@ int launch_panel(bool rowmajor, const PanelDesc &d, int nwg, hipStream_t s) {
 }
 
 int launch_larft(const double *S, int ldS, const double *tau, int nb, double *T, int ldT,
-                 hipStream_t s) {
-  hipLaunchKernelGGL(k_larft, dim3(1), dim3(kThreads), 0, s, S, ldS, tau, nb, T, ldT);
+                 hipStream_t s, const int *gate, int gate_val) {
+  hipLaunchKernelGGL(k_larft, dim3(1), dim3(kThreads), 0, s, S, ldS, tau, nb, T, ldT, gate,
+                     gate_val);
   BR_HIP_CHECK(hipGetLastError());
   return 0;
 }

@@ -61,6 +61,8 @@ def test_ex_precision_and_options_checked():
     assert br.bandred_sy2sb_ex(10, 4, 4, FAKE, 10, FAKE, 7) == -7
     o = br.Opts(2, 0)
     assert br.bandred_sy2sb_ex(10, 4, 4, FAKE, 10, FAKE, 0, o) == -8
+    o = br.Opts(1, 0, 3)
+    assert br.bandred_sy2sb_ex(10, 4, 4, FAKE, 10, FAKE, 0, o) == -8
     o = br.Opts(1, 0)
     o.reserved[3] = 1
     assert br.bandred_sy2sb_ex(10, 4, 4, FAKE, 10, FAKE, 0, o) == -8

@@ -20,19 +20,20 @@ CASES = [
 ]
 
 
-def _run(br, A, w, b, prec="fp64"):
+def _run(br, A, w, b, prec="fp64", method=0):
     m, n = A.shape
     Ad, lda = to_device_colmajor(A)
-    tq, tp = br.ge2gb(Ad, w, b, prec=prec)
+    tq, tp = br.ge2gb(Ad, w, b, prec=prec, panel_method=method)
     torch.cuda.synchronize()
     return Ad.cpu().numpy(), tq.cpu().numpy(), tp.cpu().numpy()
 
 
+@pytest.mark.parametrize("method", [0, 1], ids=["cholqr2", "percolumn"])
 @pytest.mark.parametrize("m,n,w,b,seed", CASES)
-def test_ge2gb_matches_oracle(bandred, orc, m, n, w, b, seed):
-    print(f"case ge2gb m={m} n={n} w={w} b={b} seed={seed}", flush=True)
+def test_ge2gb_matches_oracle(bandred, orc, m, n, w, b, seed, method):
+    print(f"case ge2gb m={m} n={n} w={w} b={b} seed={seed} method={method}", flush=True)
     A = inputs.ge_normal(m, n, 200 + seed)
-    Ag, tqg, tpg = _run(bandred, A, w, b)
+    Ag, tqg, tpg = _run(bandred, A, w, b, method=method)
     Ao, tqo, tpo = orc.ge2gb(A, w)
     nA = np.linalg.norm(A)
     db, dl, dr, dq, dp = ge_compare(Ag, tqg, tpg, Ao, tqo, tpo, w)
@@ -41,3 +42,14 @@ def test_ge2gb_matches_oracle(bandred, orc, m, n, w, b, seed):
     assert max(dl, dr, dq, dp) <= tol, (dl, dr, dq, dp)
     err = metrics.ge2gb_errors(A, Ag, tqg, tpg, w, svd=False)
     assert err["backward"] <= tol, err
+
+
+def test_ge2gb_banded_input_is_exact(bandred):
+    m, n, w = 300, 200, 10
+    A = inputs.ge_normal(m, n, 77)
+    i = np.arange(m)[:, None]
+    j = np.arange(n)[None, :]
+    A[~((j - i >= 0) & (j - i <= w))] = 0.0
+    Ag, tqg, tpg = _run(bandred, A, w, w)
+    assert np.all(tqg == 0.0) and np.all(tpg == 0.0)
+    assert np.array_equal(Ag, A)

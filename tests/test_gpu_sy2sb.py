@@ -30,23 +30,25 @@ CASES = [
 ]
 
 
-def _run(br, A, w, b, lda_pad=0, prec="fp64", lookahead=True):
+def _run(br, A, w, b, lda_pad=0, prec="fp64", lookahead=True, method=0):
     n = A.shape[0]
     Ad, lda = to_device_colmajor(A, n + lda_pad)
-    tau = br.sy2sb(Ad[:n] if lda_pad else Ad, w, b, prec=prec, lookahead=lookahead)
+    tau = br.sy2sb(Ad[:n] if lda_pad else Ad, w, b, prec=prec, lookahead=lookahead,
+                   panel_method=method)
     torch.cuda.synchronize()
     full = Ad.cpu().numpy()
     return full[:n, :], tau.cpu().numpy(), full
 
 
+@pytest.mark.parametrize("method", [0, 1], ids=["cholqr2", "percolumn"])
 @pytest.mark.parametrize("n,w,b,pad,seed", CASES)
-def test_sy2sb_matches_oracle(bandred, orc, n, w, b, pad, seed):
-    print(f"case sy2sb n={n} w={w} b={b} pad={pad} seed={seed}", flush=True)
+def test_sy2sb_matches_oracle(bandred, orc, n, w, b, pad, seed, method):
+    print(f"case sy2sb n={n} w={w} b={b} pad={pad} seed={seed} method={method}", flush=True)
     A = inputs.sym_normal(n, 100 + seed)
     # poison the strict upper triangle: it must be neither read nor written
     Ain = A.copy()
     Ain[np.triu_indices(n, 1)] = np.nan
-    Ag, tg, full = _run(bandred, Ain, w, b, pad)
+    Ag, tg, full = _run(bandred, Ain, w, b, pad, method=method)
     assert np.isnan(Ag[np.triu_indices(n, 1)]).all(), "upper triangle was written"
     if pad:
         assert np.isnan(full[n:, :]).all(), "rows beyond n were written"
@@ -84,6 +86,37 @@ def test_sy2sb_banded_input_is_exact(bandred):
     Ag, tg, _ = _run(bandred, A, w, w)
     assert np.all(tg == 0.0)
     assert np.array_equal(np.tril(Ag), np.tril(A))
+
+
+def test_rank_deficient_panel_falls_back(bandred, orc):
+    """A zero column inside the first panel makes the Gram matrix singular;
+    the device flag routes that panel to the per-column kernel.  The column
+    stays exactly zero through every earlier reflector, so sigma = 0 and
+    tau = 0 on both sides, and every other reflector is generic."""
+    n, w = 400, 32
+    A = inputs.sym_normal(n, 31)
+    A[w:, 5] = 0.0
+    A[5, w:] = 0.0
+    Ag, tg, _ = _run(bandred, A, w, w)
+    Ao, to = orc.sy2sb(A, w)
+    db, dr, dt = sy_compare(np.tril(Ag), tg, np.tril(Ao), to, w)
+    assert tg[5] == 0.0 and to[5] == 0.0
+    tol = 1e-14 * n
+    assert db <= tol * np.linalg.norm(A) and dr <= tol and dt <= tol, (db, dr, dt)
+
+
+def test_numerically_dependent_columns(bandred):
+    """Two proportional columns: the later one becomes zero up to rounding
+    after the earlier reflectors, so its reflector is set by rounding noise
+    (on the GPU and in the oracle alike) and only backward stability can be
+    compared."""
+    n, w = 400, 32
+    A = inputs.sym_normal(n, 32)
+    A[w:, 9] = 2.0 * A[w:, 7]
+    A[9, w:] = A[w:, 9]
+    Ag, tg, _ = _run(bandred, A, w, w)
+    err = metrics.sy2sb_errors(A, np.tril(Ag), tg, w, eig=False)
+    assert err["backward"] <= 1e-14 * n and err["orth"] <= 1e-14 * n, err
 
 
 def test_lookahead_is_bit_identical_to_serial(bandred):
