@@ -22,6 +22,7 @@
 //   3. right LQ of A[c:c+pr, c+w:n], Wtp = U Tp   (eq. updateC)
 //   4. D = A[c+pr:m, c+w:n]: D -= (D Wtp) U^T      (eq. updateD)
 #include <mutex>
+#include <algorithm>
 #include <vector>
 #include <cstdio>
 #include <cstdlib>
@@ -40,9 +41,10 @@ int hip_fail(hipError_t e, const char *what) {
 // profiling (optional): events around every launch
 // ---------------------------------------------------------------------------
 enum Cls { C_PANEL = 0, C_LARFT, C_SYMM, C_SYR2K, C_GEMM_SMALL, C_REDUCE, C_GEMM_UPD,
-           C_PANEL_SMALL, C_OTHER, C_NCLS };
+           C_PANEL_SMALL, C_OTHER, C_BATCHED, C_NCLS };
 static const char *kClsNames[C_NCLS] = {"panel_qr", "larft", "symm", "syr2k", "gemm_small",
-                                        "reduce", "gemm_update", "panel_small", "other"};
+                                        "reduce", "gemm_update", "panel_small", "other",
+                                        "batched"};
 struct ProfRec {
   int cls;
   double flops;
@@ -95,6 +97,16 @@ struct DevState {
   int *flags = nullptr;       // [0] status, [1] abort   (device)
   long long timeout_ticks = 0;
   int num_cu = 0;
+  // batched calls: pinned copy of the last uploaded matrix table, its device
+  // copy, the work counter and the per-workgroup scratch
+  BatchEntry *bt_host = nullptr;
+  BatchEntry *bt_dev = nullptr;
+  size_t bt_cap = 0;          // entries of bt_host / bt_dev
+  int64_t bt_count = -1;      // entries of the last upload
+  hipEvent_t bt_ev = nullptr; // completion of the last table upload
+  unsigned *bt_queue = nullptr;
+  double *bt_ws = nullptr;
+  int bt_wgs = 0;             // workgroups bt_ws holds
 };
 static std::mutex g_mu;
 static DevState g_dev[64];
@@ -120,6 +132,9 @@ static int dev_state(DevState **out) {
     BR_HIP_CHECK(hipMalloc((void **)&st.flags, 64));
     BR_HIP_CHECK(hipMemset(st.flags, 0, 64));
     BR_HIP_CHECK(hipEventRecord(st.done, st.aux));
+    BR_HIP_CHECK(hipEventCreateWithFlags(&st.bt_ev, hipEventDisableTiming));
+    BR_HIP_CHECK(hipEventRecord(st.bt_ev, st.aux));
+    BR_HIP_CHECK(hipMalloc((void **)&st.bt_queue, 256));
     st.init = true;
   }
   *out = &st;
@@ -581,6 +596,94 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
   return 0;
 }
 
+// ---------------------------------------------------------------------------
+// Batched SY2SB: one persistent launch over a table of matrices sorted by
+// decreasing order; matrices the kernel cannot hold (b > 16 or n - w > 1024)
+// go through the single-matrix path on the same stream afterwards.
+// ---------------------------------------------------------------------------
+static int batched_impl(int64_t count, const int64_t *n, int w, int b, double *const *A,
+                        const int64_t *lda, double *const *tau, int prec, hipStream_t s) {
+  DevState *st = nullptr;
+  int rc = dev_state(&st);
+  if (rc) return rc;
+  std::vector<BatchEntry> tab;
+  std::vector<int64_t> big;
+  tab.reserve((size_t)count);
+  for (int64_t i = 0; i < count; ++i) {
+    if (n[i] <= w) continue;  // already banded, no reflectors
+    if (b <= batched_max_block() && n[i] - w <= batched_max_trailing())
+      tab.push_back(BatchEntry{A[i], tau[i], lda[i], (int)n[i], 0});
+    else
+      big.push_back(i);
+  }
+  std::stable_sort(tab.begin(), tab.end(),
+                   [](const BatchEntry &x, const BatchEntry &y) { return x.n > y.n; });
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  BR_HIP_CHECK(hipStreamIsCapturing(s, &cap));
+  const bool capturing = cap != hipStreamCaptureStatusNone;
+  if (!tab.empty()) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    const int nwg = (int)std::min<int64_t>((int64_t)tab.size(), st->num_cu);
+    const size_t tb = tab.size() * sizeof(BatchEntry);
+    const bool same = st->bt_count == (int64_t)tab.size() && memcmp(st->bt_host, tab.data(), tb) == 0;
+    if (capturing && (!same || nwg > st->bt_wgs)) return BANDRED_ERR_UNSUPPORTED;
+    if (!capturing) BR_HIP_CHECK(hipStreamWaitEvent(s, st->done, 0));
+    if (nwg > st->bt_wgs) {
+      BR_HIP_CHECK(hipEventSynchronize(st->done));
+      if (st->bt_ws) BR_HIP_CHECK(hipFree(st->bt_ws));
+      st->bt_ws = nullptr;
+      st->bt_wgs = 0;
+      if (hipMalloc((void **)&st->bt_ws, (size_t)nwg * batched_ws_doubles() * sizeof(double)) !=
+          hipSuccess) {
+        (void)hipGetLastError();
+        st->bt_ws = nullptr;
+        return BANDRED_ERR_ALLOC;
+      }
+      st->bt_wgs = nwg;
+    }
+    if (!same) {
+      BR_HIP_CHECK(hipEventSynchronize(st->bt_ev));  // the pinned copy is free again
+      if (tab.size() > st->bt_cap) {
+        BR_HIP_CHECK(hipEventSynchronize(st->done));  // no kernel reads the old table
+        if (st->bt_host) BR_HIP_CHECK(hipHostFree(st->bt_host));
+        if (st->bt_dev) BR_HIP_CHECK(hipFree(st->bt_dev));
+        st->bt_host = nullptr;
+        st->bt_dev = nullptr;
+        st->bt_cap = 0;
+        st->bt_count = -1;
+        const size_t cap_e = tab.size() + tab.size() / 4 + 64;
+        if (hipHostMalloc((void **)&st->bt_host, cap_e * sizeof(BatchEntry), hipHostMallocDefault) !=
+                hipSuccess ||
+            hipMalloc((void **)&st->bt_dev, cap_e * sizeof(BatchEntry)) != hipSuccess) {
+          (void)hipGetLastError();
+          return BANDRED_ERR_ALLOC;
+        }
+        st->bt_cap = cap_e;
+      }
+      memcpy(st->bt_host, tab.data(), tb);
+      BR_HIP_CHECK(hipMemcpyAsync(st->bt_dev, st->bt_host, tb, hipMemcpyHostToDevice, s));
+      BR_HIP_CHECK(hipEventRecord(st->bt_ev, s));
+      st->bt_count = (int64_t)tab.size();
+    }
+    rc = launch_fill_u32(st->bt_queue, 1, 0u, s);
+    if (rc) return rc;
+    double flops = 0.0;
+    for (const BatchEntry &e : tab) flops += 4.0 / 3.0 * (double)e.n * e.n * e.n;
+    {
+      ProfScope ps(C_BATCHED, flops, s);
+      rc = launch_batched(prec, st->bt_dev, (int)tab.size(), w, b, st->bt_queue, st->bt_ws, nwg, s);
+    }
+    if (rc) return rc;
+    if (!capturing) BR_HIP_CHECK(hipEventRecord(st->done, s));
+  }
+  if (!big.empty() && capturing) return BANDRED_ERR_UNSUPPORTED;
+  for (int64_t i : big) {
+    rc = sy2sb_impl(n[i], w, b, A[i], lda[i], tau[i], prec, nullptr, s);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
 static int read_status(hipStream_t s) {
   DevState *st = nullptr;
   int rc = dev_state(&st);
@@ -692,8 +795,9 @@ int bandred_sy2sb_batched(int64_t count, const int64_t *n, int64_t w, int64_t b,
     if (lda[i] < (n[i] > 1 ? n[i] : 1)) return -6;
     if (n[i] > w && tau[i] == nullptr) return -7;
   }
-  (void)stream;
-  return BANDRED_ERR_UNSUPPORTED;
+  if (count == 0) return 0;
+  if (w > ((int64_t)1 << 30)) return BANDRED_ERR_UNSUPPORTED;
+  return batched_impl(count, n, (int)w, (int)b, A, lda, tau, prec, (hipStream_t)stream);
 }
 
 const char *bandred_status_string(int status) {

@@ -100,4 +100,18 @@ constexpr int kPackedMax = kNbMax * (kNbMax + 1) / 2;
 int launch_fill(double *p, int64_t count, double v, hipStream_t s);
 int launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t s);
 int panel_lds_bytes(int R, int nb);
+
+// One matrix of a batched SY2SB call (device table entry).
+struct BatchEntry {
+  double *A;
+  double *tau;
+  int64_t lda;
+  int n;
+  int pad;
+};
+int launch_batched(int prec, const BatchEntry *table, int count, int w, int b, unsigned *queue,
+                   double *ws, int nwg, hipStream_t s);
+int64_t batched_ws_doubles();   // scratch doubles per workgroup
+int batched_max_trailing();     // largest n - w the batched kernel holds
+int batched_max_block();        // largest b of the batched kernel
 }  // namespace br
