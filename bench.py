@@ -92,6 +92,192 @@ def cpu_baseline(p, A_dev):
                       f"oracle's full-matrix copy in and out"}
 
 
+def batch_bytes(ns, w, b):
+    """Algorithmic HBM bytes of the batched reduction: per panel of trailing
+    order j, the lower triangle of A2 is read by X = A2 Wt and read and
+    written by the rank-2b update (3 x 8 j^2 / 2 bytes), plus the panel read
+    and written once (16 j b bytes)."""
+    tot = 0.0
+    for n in ns:
+        for c in range(0, max(n - w - 1, 0), b):
+            j = n - c - w
+            tot += 12.0 * j * j + 16.0 * j * b
+    return tot
+
+
+def bench_batched(args, br, inputs, metrics):
+    """Batched SY2SB: 2048 matrices of orders drawn from {64, 96, ..., 1024},
+    w = b = 16, reduced by one persistent launch captured in a HIP graph.
+    Also timed: the same call without the graph, the FP32-update form and
+    one pass of per-matrix calls of the single-matrix path."""
+    import numpy as np
+    import torch
+
+    stream = torch.cuda.current_stream()
+    log(f"bench: building workload {args.workload} on the GPU")
+    p = inputs.make_on_device(args.workload, device="cuda")
+    w, b = p["w"], p["b"]
+    sizes = [int(x) for x in p["sizes"]]
+    offs = [int(x) for x in p["offsets"]]
+    flat0 = p["flat"]
+    flat = flat0.clone()
+    count = len(sizes)
+    ptrs = [flat.data_ptr() + 8 * o for o in offs]
+    taus = torch.zeros(sum(max(n - w, 1) for n in sizes), dtype=torch.float64, device="cuda")
+    toffs = np.concatenate([[0], np.cumsum([max(n - w, 1) for n in sizes])])[:-1]
+    tptrs = [taus.data_ptr() + 8 * int(o) for o in toffs]
+    flops = sum(4.0 * n ** 3 / 3.0 for n in sizes)
+    nbytes = batch_bytes(sizes, w, b)
+
+    def restore():
+        flat.copy_(flat0)
+
+    def call(prec, s):
+        rc = br.bandred_sy2sb_batched(count, sizes, w, b, ptrs, sizes, tptrs, prec, s)
+        if rc != 0:
+            raise RuntimeError(f"bandred_sy2sb_batched: {br.status_string(rc)}")
+
+    # eager warm-up (uploads the matrix table), then capture one call per form
+    graphs = {}
+    for prec in (0, 1):
+        restore()
+        call(prec, stream.cuda_stream)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        cs = torch.cuda.Stream()
+        cs.wait_stream(stream)
+        with torch.cuda.stream(cs):
+            with torch.cuda.graph(g, stream=cs):
+                call(prec, cs.cuda_stream)
+        torch.cuda.synchronize()
+        graphs[prec] = g
+    run64 = graphs[0].replay
+    log(f"bench: warmup {args.warmup}")
+    for _ in range(args.warmup):
+        restore()
+        run64()
+    torch.cuda.synchronize()
+    log(f"bench: timing {args.steps} steps (graph replay)")
+    t_wall = time.perf_counter()
+    times = time_steps(run64, restore, args.steps, stream)
+    t_wall = time.perf_counter() - t_wall
+    ms = statistics.median(times)
+    gflops = flops / (ms / 1e3) / 1e9
+    log(f"bench: fp64 steps ms = {[round(t, 2) for t in times]}  -> {gflops:.1f} GFLOP/s")
+    if args.profile_only:
+        print(json.dumps({"metric": METRIC, "value": gflops, "unit": "GFLOP/s", "ms_per_step": ms}))
+        return
+
+    acc = {}
+    if not args.no_accuracy:
+        log("bench: accuracy of sampled matrices of the FP64 result")
+        order = np.argsort(sizes)
+        pick = sorted(set(int(order[i]) for i in np.linspace(0, count - 1, 8).round().astype(int)))
+        worst = {}
+        for k in pick:
+            n, o = sizes[k], offs[k]
+            A0 = flat0[o:o + n * n].view(n, n).T  # column-major view
+            A0s = torch.tril(A0) + torch.tril(A0, -1).T
+            Ak = flat[o:o + n * n].view(n, n).T
+            tk = taus[int(toffs[k]):int(toffs[k]) + max(n - w, 1)]
+            e = metrics.sy2sb_errors(A0s, torch.tril(Ak), tk[:max(n - w, 0)], w, eig=False)
+            for key, v in e.items():
+                if v is not None:
+                    worst[key] = max(worst.get(key, 0.0), v)
+        acc = dict(worst, sampled_orders=[sizes[k] for k in pick])
+
+    # per-launch device time of the persistent kernel
+    restore()
+    torch.cuda.synchronize()
+    br.bandred_profile_enable(True)
+    call(0, stream.cuda_stream)
+    torch.cuda.synchronize()
+    prof = br.bandred_profile_read()
+    br.bandred_profile_enable(False)
+    d = prof["batched"]
+    kms = d["ms"] / max(d["launches"], 1)
+    gbs = nbytes / (kms / 1e3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "k_batched<fp64>", "achieved": gbs, "peak": 8000.0,
+                "unit": "GB/s", "frac": gbs / 8000.0, "traffic": None,
+                "avg_launch_ms": kms, "launches": d["launches"],
+                "algorithmic_bytes": nbytes,
+                "mfma_tflops": flops / (kms / 1e3) / 1e12,
+                "mfma_frac": flops / (kms / 1e3) / 1e12 / PEAK_TFLOPS["fp64"]}
+
+    forms = {}
+    if not args.no_forms:
+        log("bench: eager call (no graph)")
+        tt = time_steps(lambda: call(0, stream.cuda_stream), restore, max(2, args.steps // 2), stream)
+        m2 = statistics.median(tt)
+        forms["fp64_eager"] = {"gflops": flops / (m2 / 1e3) / 1e9, "ms_per_step": m2}
+        log("bench: form fp32 (graph replay)")
+        tt = time_steps(graphs[1].replay, restore, max(2, args.steps // 2), stream)
+        m2 = statistics.median(tt)
+        f = {"gflops": flops / (m2 / 1e3) / 1e9, "ms_per_step": m2, "speedup_vs_fp64": ms / m2}
+        if not args.no_accuracy:
+            k = int(np.argmax(sizes))
+            n, o = sizes[k], offs[k]
+            A0 = flat0[o:o + n * n].view(n, n).T
+            A0s = torch.tril(A0) + torch.tril(A0, -1).T
+            Ak = flat[o:o + n * n].view(n, n).T
+            tk = taus[int(toffs[k]):int(toffs[k]) + max(n - w, 0)]
+            f["backward_largest"] = metrics.sy2sb_errors(A0s, torch.tril(Ak), tk, w, eig=False)["backward"]
+        forms["fp32"] = f
+        log("bench: per-matrix calls of the single-matrix path (one pass)")
+        restore()
+        torch.cuda.synchronize()
+        st = torch.cuda.Event(enable_timing=True)
+        en = torch.cuda.Event(enable_timing=True)
+        st.record(stream)
+        for k in range(count):
+            rc = br.bandred_sy2sb_ex(sizes[k], w, b, ptrs[k], sizes[k], tptrs[k], 0, None,
+                                     stream.cuda_stream)
+            if rc != 0:
+                raise RuntimeError(br.status_string(rc))
+        en.record(stream)
+        torch.cuda.synchronize()
+        m3 = st.elapsed_time(en)
+        forms["per_matrix_launches"] = {"gflops": flops / (m3 / 1e3) / 1e9, "ms_per_step": m3,
+                                        "batched_speedup": m3 / ms}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline (oracle, bounded sample)")
+        import oracle
+
+        orc = oracle.get()
+        done, fl, t0 = 0, 0.0, time.perf_counter()
+        while done < count and time.perf_counter() - t0 < 15.0:
+            n, o = sizes[done], offs[done]
+            A0 = flat0[o:o + n * n].view(n, n).T.cpu().numpy()
+            A0 = np.tril(A0) + np.tril(A0, -1).T
+            orc.sy2sb(A0, w)
+            fl += 4.0 * n ** 3 / 3.0
+            done += 1
+        dt = time.perf_counter() - t0
+        cpu = {"value": fl / dt / 1e9, "unit": "GFLOP/s", "cores": orc.threads(), "kind": "oracle",
+               "sample": f"the first {done} of {count} matrices of the batch in generation order "
+                         f"({dt:.1f} s incl. host copies)"}
+
+    res = {
+        "metric": METRIC, "value": gflops, "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "count": count, "orders": "uniform over {64, 96, ..., 1024}",
+                   "w": w, "b": b, "prec": "fp64", "launch": "one persistent kernel, HIP graph replay",
+                   "input": f"i.i.d. N(0,1) lower triangles, seed {p['seed']}"},
+        "pct_fp64_peak": 100.0 * gflops / 1e3 / PEAK_TFLOPS["fp64"],
+        "step_ms_all": [round(t, 3) for t in times],
+        "timed_wall_s": t_wall,
+        "accuracy": acc,
+        "roofline": roofline,
+        "forms": forms,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +302,8 @@ def main():
 
     br.load()
     torch.cuda.set_device(0)
+    if inputs.WORKLOADS[args.workload]["kind"] == "batch":
+        return bench_batched(args, br, inputs, metrics)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
 

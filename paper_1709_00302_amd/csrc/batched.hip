@@ -16,9 +16,12 @@
 //   5. M = Wt^T X, W = X - 1/2 V M;
 //   6. A2 -= W V^T + V W^T on the lower blocks.
 // Products run on 16 x 16 x 4 MFMA blocks: FP64, or FP32 for the trailing
-// products 4 and 6 in the FP32-update form.  V, Wt and W live in a
-// per-workgroup scratch, row-major with 16 columns and rows padded to a
-// multiple of 16, so one 16 x 16 block is 2 KB contiguous.
+// products 4 and 6 in the FP32-update form.  V and W live in a per-workgroup
+// scratch column-major and Wt row-major, rows padded to a multiple of 16, so
+// that every operand fragment of the O(j^2) steps 4 and 6 is read with 16
+// consecutive lanes on 16 consecutive doubles.  In 4 and 6 each wave owns
+// whole column blocks (dealt in snake order) and loads the next block's
+// operands before it uses the current ones.
 #include "common.hpp"
 
 namespace br {
@@ -34,7 +37,7 @@ struct BatchDesc {
   int count;
   int w, b;
   unsigned *queue;
-  double *ws;          // per-workgroup scratch: V, Wt, W, each kBJMax x 16
+  double *ws;          // per-workgroup scratch: V, W, Wt, each kBJMax x 16
   int64_t ws_stride;   // doubles per workgroup
 };
 
@@ -118,15 +121,6 @@ __device__ __forceinline__ void reduce_waves(BatchLds &L, const v4d &acc, double
   __syncthreads();
 }
 
-// Next lower-triangle block, kBW blocks further in column order: column K
-// holds row blocks K .. nbk-1.
-__device__ __forceinline__ void next_lower(int &K, int &I, int nbk) {
-  while (K < nbk && I >= nbk) {
-    I = I - nbk + K + 1;
-    ++K;
-  }
-}
-
 // Column I of the panel QR (I fixed at compile time so that the register
 // panel a[][] is never indexed dynamically): one workgroup reduction gives the
 // sums s_k = sum_{rho > I} a(rho, I) a(rho, k) and the pivot row; every thread
@@ -160,22 +154,22 @@ __device__ __forceinline__ void house_col(double (&a)[kRPT][kBN], BatchLds &L, i
   __syncthreads();
   // reflector: beta = -sign(alpha) ||(alpha, x)||, v = x / (alpha - beta)
   const double alpha = L.prow[I & 1][I], sig2 = L.tot[I];
-  double tau = 0.0, dv = 1.0, beta = alpha;
+  double tau = 0.0, dv = 0.0, beta = alpha;
   if (sig2 != 0.0) {
     const double nrm = sqrt(alpha * alpha + sig2);
     beta = (alpha < 0.0) ? nrm : -nrm;
     tau = (beta - alpha) / beta;
-    dv = alpha - beta;
+    dv = 1.0 / (alpha - beta);
   }
   if (tau != 0.0) {
-    // column k: a_k -= tau v (v^T a_k) with v^T a_k = p_k + s_k / dv
+    // column k: a_k -= tau v (v^T a_k) with v^T a_k = p_k + s_k / (alpha - beta)
     double f[kBN];
 #pragma unroll
-    for (int k = I + 1; k < kBN; ++k) f[k] = tau * (L.prow[I & 1][k] + L.tot[k] / dv);
+    for (int k = I + 1; k < kBN; ++k) f[k] = tau * (L.prow[I & 1][k] + L.tot[k] * dv);
 #pragma unroll
     for (int s = 0; s < kRPT; ++s) {
       if (s > 0 || tid > I) {
-        const double v = a[s][I] / dv;
+        const double v = a[s][I] * dv;
         a[s][I] = v;
 #pragma unroll
         for (int k = I + 1; k < kBN; ++k) a[s][k] -= v * f[k];
@@ -211,9 +205,11 @@ template <int PREC>
 __global__ __launch_bounds__(kBT) void k_batched(BatchDesc d) {
   __shared__ BatchLds L;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double *V = d.ws + (int64_t)blockIdx.x * d.ws_stride;
-  double *Wt = V + (int64_t)kBJMax * kBN;
-  double *W = Wt + (int64_t)kBJMax * kBN;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  // scratch: V and W column-major (ld kBJMax), Wt = V T row-major (16 columns)
+  double *Vc = d.ws + (int64_t)blockIdx.x * d.ws_stride;
+  double *Wc = Vc + (int64_t)kBJMax * kBN;
+  double *Wt = Wc + (int64_t)kBJMax * kBN;
   const int w = d.w, b = d.b;
   const v4d z64 = {0.0, 0.0, 0.0, 0.0};
   const v4f z32 = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -261,7 +257,7 @@ __global__ __launch_bounds__(kBT) void k_batched(BatchDesc d) {
           for (int k = 0; k < kBN; ++k) {
             double v = 0.0;
             if (k < pb && rho < j) v = (rho == k) ? 1.0 : (rho > k ? a[s][k] : 0.0);
-            V[(int64_t)rho * kBN + k] = v;
+            Vc[(int64_t)k * kBJMax + rho] = v;
           }
         }
       }
@@ -274,28 +270,26 @@ __global__ __launch_bounds__(kBT) void k_batched(BatchDesc d) {
         for (int I = wave; I < nbk; I += kBW) {
           double av[4];
 #pragma unroll
-          for (int s = 0; s < 4; ++s) av[s] = V[(int64_t)(I * kBN + (lane >> 4) + 4 * s) * kBN + (lane & 15)];
+          for (int s = 0; s < 4; ++s) av[s] = Vc[(int64_t)l16 * kBJMax + I * kBN + l4 + 4 * s];
           mma16<P_F64>(acc, acc32, av, av);  // V^T(l%16, k) and V(k, l%16) are the same value
         }
         reduce_waves(L, acc, L.S, tid, lane, wave);
       }
       if (wave == 0) {
         // T(i,i) = tau_i, T(0:i, i) = -tau_i T(0:i, 0:i) S(0:i, i); lane l
-        // owns row l and reads only its own row of T
+        // holds row l of T
+        double trow[kBN];
+#pragma unroll
         for (int i = 0; i < kBN; ++i) {
-          if (lane < kBN) {
-            double v = 0.0;
-            if (i < pb) {
-              if (lane < i) {
-                double acc = 0.0;
-                for (int m = lane; m < i; ++m) acc += L.T[lane * kBN + m] * L.S[m * kBN + i];
-                v = -L.tau[i] * acc;
-              } else if (lane == i) {
-                v = L.tau[i];
-              }
-            }
-            L.T[lane * kBN + i] = v;
-          }
+          double acc = 0.0;
+#pragma unroll
+          for (int m = 0; m < i; ++m) acc += trow[m] * L.S[m * kBN + i];
+          const double ti = (i < pb) ? L.tau[i] : 0.0;
+          trow[i] = (lane < i) ? -ti * acc : (lane == i ? ti : 0.0);
+        }
+        if (lane < kBN) {
+#pragma unroll
+          for (int i = 0; i < kBN; ++i) L.T[lane * kBN + i] = trow[i];
         }
       }
       __syncthreads();
@@ -305,13 +299,13 @@ __global__ __launch_bounds__(kBT) void k_batched(BatchDesc d) {
         double av[4], bv[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          av[s] = V[(int64_t)(I * kBN + (lane & 15)) * kBN + (lane >> 4) + 4 * s];
-          bv[s] = L.T[((lane >> 4) + 4 * s) * kBN + (lane & 15)];
+          av[s] = Vc[(int64_t)(l4 + 4 * s) * kBJMax + I * kBN + l16];
+          bv[s] = L.T[(l4 + 4 * s) * kBN + l16];
         }
         mma16<P_F64>(acc, acc32, av, bv);
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          Wt[(int64_t)(I * kBN + orow<P_F64>(lane, e)) * kBN + (lane & 15)] = acc[e];
+          Wt[(int64_t)(I * kBN + orow<P_F64>(lane, e)) * kBN + l16] = acc[e];
       }
       __syncthreads();
 
@@ -327,8 +321,8 @@ __global__ __launch_bounds__(kBT) void k_batched(BatchDesc d) {
             double av[4], bv[4];
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-              const int row = I * kBN + (lane >> 4) + 4 * s, col = Q * kBN + (lane & 15);
-              av[s] = Wt[(int64_t)row * kBN + (lane & 15)];
+              const int row = I * kBN + l4 + 4 * s, col = Q * kBN + l16;
+              av[s] = Wt[(int64_t)row * kBN + l16];
               bv[s] = (row < j && col < a1w) ? A1[row + (int64_t)col * lda] : 0.0;
             }
             mma16<P_F64>(acc, acc32, av, bv);
@@ -341,13 +335,13 @@ __global__ __launch_bounds__(kBT) void k_batched(BatchDesc d) {
             double av[4], bv[4];
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-              av[s] = L.M[((lane >> 4) + 4 * s) * kBN + (lane & 15)];
-              bv[s] = V[(int64_t)(I * kBN + (lane & 15)) * kBN + (lane >> 4) + 4 * s];
+              av[s] = L.M[(l4 + 4 * s) * kBN + l16];
+              bv[s] = Vc[(int64_t)(l4 + 4 * s) * kBJMax + I * kBN + l16];
             }
             mma16<P_F64>(o, o32, av, bv);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-              const int row = I * kBN + (lane & 15), col = Q * kBN + orow<P_F64>(lane, e);
+              const int row = I * kBN + l16, col = Q * kBN + orow<P_F64>(lane, e);
               if (row < j && col < a1w) A1[row + (int64_t)col * lda] -= o[e];
             }
           }
@@ -356,13 +350,15 @@ __global__ __launch_bounds__(kBT) void k_batched(BatchDesc d) {
       }
 
       // ---- 4. X = A2 Wt from the lower blocks of A2 ----
+      // Wave-owned column blocks K in snake order (column K holds nbk - K
+      // blocks); the next block's operands are loaded before the current
+      // block is used.
       double *A2 = A + r + (int64_t)r * lda;
       for (int q = tid; q < nbk * kBN * kBN; q += kBT) L.X[q] = 0.0;
       __syncthreads();
       {
         double *tile = L.scr[wave];
         for (int kk = wave; kk < nbk + kBW; kk += kBW) {
-          // column blocks dealt in snake order (column K holds nbk - K blocks)
           const int round = kk / kBW, pos = kk % kBW;
           const int K = round * kBW + ((round & 1) ? kBW - 1 - pos : pos);
           if (K >= nbk) continue;
@@ -370,49 +366,60 @@ __global__ __launch_bounds__(kBT) void k_batched(BatchDesc d) {
           v4f xk32 = z32;
           double wtk[4];
 #pragma unroll
-          for (int s = 0; s < 4; ++s) wtk[s] = Wt[(int64_t)(K * kBN + (lane >> 4) + 4 * s) * kBN + (lane & 15)];
-          for (int I = K; I < nbk; ++I) {
-            // lane l holds A_IK(l%16, l/16 + 4s)
-            double ak[4];
+          for (int s = 0; s < 4; ++s) wtk[s] = Wt[(int64_t)(K * kBN + l4 + 4 * s) * kBN + l16];
+          // lane l holds A_IK(l%16, l/16 + 4s); the diagonal block is mirrored
+          auto load_blk = [&](int I, double (&ak)[4], double (&wti)[4]) {
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-              const int row = I * kBN + (lane & 15), col = K * kBN + (lane >> 4) + 4 * s;
+              const int row = I * kBN + l16, col = K * kBN + l4 + 4 * s;
               double v = 0.0;
-              if (row < j && col < j) v = (row >= col) ? A2[row + (int64_t)col * lda] : A2[col + (int64_t)row * lda];
+              if (row < j && col < j)
+                v = (row >= col) ? A2[row + (int64_t)col * lda] : A2[col + (int64_t)row * lda];
               ak[s] = v;
+              wti[s] = Wt[(int64_t)(I * kBN + l4 + 4 * s) * kBN + l16];
             }
+          };
+          double ak[4], wti[4];
+          load_blk(K, ak, wti);
+          for (int I = K; I < nbk; ++I) {
+            double akn[4], wtin[4];
+            if (I + 1 < nbk) load_blk(I + 1, akn, wtin);
             v4d o = z64;
             v4f o32 = z32;
             mma16<PREC>(o, o32, ak, wtk);
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-              atomicAdd(&L.X[(I * kBN + orow<PREC>(lane, e)) * kBN + (lane & 15)], accv<PREC>(o, o32, e));
+              atomicAdd(&L.X[(I * kBN + orow<PREC>(lane, e)) * kBN + l16], accv<PREC>(o, o32, e));
             if (I > K) {
 #pragma unroll
-              for (int s = 0; s < 4; ++s) tile[((lane >> 4) + 4 * s) * kBN + (lane & 15)] = ak[s];
+              for (int s = 0; s < 4; ++s) tile[(l4 + 4 * s) * kBN + l16] = ak[s];
               __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
               __builtin_amdgcn_wave_barrier();
               __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-              double at[4], wti[4];
+              double at[4];
 #pragma unroll
-              for (int s = 0; s < 4; ++s) {
-                at[s] = tile[(lane & 15) * kBN + (lane >> 4) + 4 * s];  // A_IK(l/16 + 4s, l%16)
-                wti[s] = Wt[(int64_t)(I * kBN + (lane >> 4) + 4 * s) * kBN + (lane & 15)];
-              }
+              for (int s = 0; s < 4; ++s) at[s] = tile[l16 * kBN + l4 + 4 * s];  // A_IK(l/16 + 4s, l%16)
               __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
               __builtin_amdgcn_wave_barrier();
               __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
               mma16<PREC>(xk, xk32, at, wti);
             }
+            if (I + 1 < nbk) {
+#pragma unroll
+              for (int s = 0; s < 4; ++s) {
+                ak[s] = akn[s];
+                wti[s] = wtin[s];
+              }
+            }
           }
 #pragma unroll
           for (int e = 0; e < 4; ++e)
-            atomicAdd(&L.X[(K * kBN + orow<PREC>(lane, e)) * kBN + (lane & 15)], accv<PREC>(xk, xk32, e));
+            atomicAdd(&L.X[(K * kBN + orow<PREC>(lane, e)) * kBN + l16], accv<PREC>(xk, xk32, e));
         }
       }
       __syncthreads();
 
-      // ---- 5. M = Wt^T X; W = X - 1/2 V M ----
+      // ---- 5. M = Wt^T X; W = X - 1/2 V M (stored column-major) ----
       {
         v4d acc = z64;
         v4f acc32 = z32;
@@ -420,9 +427,9 @@ __global__ __launch_bounds__(kBT) void k_batched(BatchDesc d) {
           double av[4], bv[4];
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
-            const int row = I * kBN + (lane >> 4) + 4 * s;
-            av[s] = Wt[(int64_t)row * kBN + (lane & 15)];
-            bv[s] = L.X[row * kBN + (lane & 15)];
+            const int row = I * kBN + l4 + 4 * s;
+            av[s] = Wt[(int64_t)row * kBN + l16];
+            bv[s] = L.X[row * kBN + l16];
           }
           mma16<P_F64>(acc, acc32, av, bv);
         }
@@ -434,47 +441,69 @@ __global__ __launch_bounds__(kBT) void k_batched(BatchDesc d) {
         double av[4], bv[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          av[s] = V[(int64_t)(I * kBN + (lane & 15)) * kBN + (lane >> 4) + 4 * s];
-          bv[s] = L.M[((lane >> 4) + 4 * s) * kBN + (lane & 15)];
+          av[s] = Vc[(int64_t)(l4 + 4 * s) * kBJMax + I * kBN + l16];
+          bv[s] = L.M[(l4 + 4 * s) * kBN + l16];
         }
         mma16<P_F64>(o, o32, av, bv);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int row = I * kBN + orow<P_F64>(lane, e);
-          W[(int64_t)row * kBN + (lane & 15)] = L.X[row * kBN + (lane & 15)] - 0.5 * o[e];
+          Wc[(int64_t)l16 * kBJMax + row] = L.X[row * kBN + l16] - 0.5 * o[e];
         }
       }
       __syncthreads();
 
       // ---- 6. A2 -= W V^T + V W^T on the lower blocks ----
-      {
-        int K = 0, I = wave;
-        next_lower(K, I, nbk);
-        while (K < nbk) {
-          // D(a, c) = sum_k V_K(a, k) W_I(c, k) + W_K(a, k) V_I(c, k)
-          //         = (W_I V_K^T + V_I W_K^T)(c, a): lanes run down rows of block I
-          v4d o = z64;
-          v4f o32 = z32;
-          double av[4], bv[4];
+      // Wave-owned column blocks as in 4: V_K, W_K stay in registers,
+      // the next row block's operands are loaded ahead.
+      for (int kk = wave; kk < nbk + kBW; kk += kBW) {
+        const int round = kk / kBW, pos = kk % kBW;
+        const int K = round * kBW + ((round & 1) ? kBW - 1 - pos : pos);
+        if (K >= nbk) continue;
+        // A operands: V_K(a, k), W_K(a, k) with a = l%16, k = l/16 + 4s
+        double vk[4], wk[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          vk[s] = Vc[(int64_t)(l4 + 4 * s) * kBJMax + K * kBN + l16];
+          wk[s] = Wc[(int64_t)(l4 + 4 * s) * kBJMax + K * kBN + l16];
+        }
+        // B operands W_I(c, k), V_I(c, k) with c = l%16; lane holds
+        // A2(I*16 + c, K*16 + orow(e))
+        auto load_blk = [&](int I, double (&wi)[4], double (&vi)[4], double (&ai)[4]) {
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
-            av[s] = V[(int64_t)(K * kBN + (lane & 15)) * kBN + (lane >> 4) + 4 * s];
-            bv[s] = W[(int64_t)(I * kBN + (lane & 15)) * kBN + (lane >> 4) + 4 * s];
+            wi[s] = Wc[(int64_t)(l4 + 4 * s) * kBJMax + I * kBN + l16];
+            vi[s] = Vc[(int64_t)(l4 + 4 * s) * kBJMax + I * kBN + l16];
           }
-          mma16<PREC>(o, o32, av, bv);
-#pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            av[s] = W[(int64_t)(K * kBN + (lane & 15)) * kBN + (lane >> 4) + 4 * s];
-            bv[s] = V[(int64_t)(I * kBN + (lane & 15)) * kBN + (lane >> 4) + 4 * s];
-          }
-          mma16<PREC>(o, o32, av, bv);
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const int row = I * kBN + (lane & 15), col = K * kBN + orow<PREC>(lane, e);
-            if (row < j && row >= col) A2[row + (int64_t)col * lda] -= accv<PREC>(o, o32, e);
+            const int row = I * kBN + l16, col = K * kBN + orow<PREC>(lane, e);
+            ai[e] = (row < j && row >= col) ? A2[row + (int64_t)col * lda] : 0.0;
           }
-          I += kBW;
-          next_lower(K, I, nbk);
+        };
+        double wi[4], vi[4], ai[4];
+        load_blk(K, wi, vi, ai);
+        for (int I = K; I < nbk; ++I) {
+          double win[4], vin[4], ain[4];
+          if (I + 1 < nbk) load_blk(I + 1, win, vin, ain);
+          // D(a, c) = sum_k V_K(a, k) W_I(c, k) + W_K(a, k) V_I(c, k)
+          v4d o = z64;
+          v4f o32 = z32;
+          mma16<PREC>(o, o32, vk, wi);
+          mma16<PREC>(o, o32, wk, vi);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int row = I * kBN + l16, col = K * kBN + orow<PREC>(lane, e);
+            if (row < j && row >= col) A2[row + (int64_t)col * lda] = ai[e] - accv<PREC>(o, o32, e);
+          }
+          if (I + 1 < nbk) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+              wi[s] = win[s];
+              vi[s] = vin[s];
+              ai[s] = ain[s];
+            }
+          }
         }
       }
       __syncthreads();

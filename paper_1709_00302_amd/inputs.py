@@ -176,6 +176,17 @@ def make_on_device(name: str, device="cuda"):
         V = haar_t(n, n)
         A = (U * sig) @ V.T
         p["sigma"] = sig.cpu().numpy()
+    elif kind == "batch":
+        # one flat buffer; matrix k is the column-major n_k x n_k block at
+        # offsets[k] (lda = n_k).  Entries i.i.d. N(0,1); the reduction reads
+        # the lower triangle only, so the symmetric matrix is its lower
+        # triangle mirrored.
+        sizes = batch_sizes(p["count"], p["seed"])
+        offs = np.concatenate([[0], np.cumsum(sizes.astype(np.int64) ** 2)])
+        p["sizes"] = sizes
+        p["offsets"] = offs[:-1]
+        p["flat"] = torch.randn(int(offs[-1]), generator=gen, device=device, dtype=f64)
+        return p
     else:
         raise ValueError(kind)
     # column-major storage: keep a row-major buffer of A^T
