@@ -611,7 +611,8 @@ static int batched_impl(int64_t count, const int64_t *n, int w, int b, double *c
   tab.reserve((size_t)count);
   for (int64_t i = 0; i < count; ++i) {
     if (n[i] <= w) continue;  // already banded, no reflectors
-    if (b <= batched_max_block() && n[i] - w <= batched_max_trailing())
+    if (b <= batched_max_block() && n[i] - w <= batched_max_trailing() &&
+        lda[i] * n[i] < ((int64_t)1 << 29))  // 32-bit element offsets in the kernel
       tab.push_back(BatchEntry{A[i], tau[i], lda[i], (int)n[i], 0});
     else
       big.push_back(i);
