@@ -62,46 +62,60 @@ def time_steps(run, restore, steps, stream):
 
 
 def cpu_baseline(p, A_dev):
-    """The oracle as it stands, on the first k reflector columns of the same
-    matrix (a bounded sample), rated with the same per-column flop model."""
+    """The oracle as it stands, on the first k reflector columns (steps) of
+    the same matrix (a bounded sample), rated with the same flop model."""
     import numpy as np
 
     import oracle
 
     orc = oracle.get()
+    is_ge = "m" in p
     n, w = p["n"], p["w"]
+    m = p["m"] if is_ge else n
     A = A_dev.cpu().numpy()
+    run = (lambda k: orc.ge2gb(A, w, ncols=k)) if is_ge else (lambda k: orc.sy2sb(A, w, ncols=k))
     # per-column cost from two short runs (the oracle's full-matrix copy in
     # and out is a fixed cost), then a sample of about 20 s
     t0 = time.perf_counter()
-    orc.sy2sb(A, w, ncols=2)
+    run(2)
     t2 = time.perf_counter() - t0
     t0 = time.perf_counter()
-    orc.sy2sb(A, w, ncols=10)
+    run(10)
     t10 = time.perf_counter() - t0
     per_col = max((t10 - t2) / 8.0, 1e-4)
     fixed = max(t2 - 2.0 * per_col, 0.0)
-    k = int(max(10, min(n - w - 1, (20.0 - fixed) / per_col)))
+    ncol = n if is_ge else n - w - 1
+    k = int(max(10, min(ncol, (20.0 - fixed) / per_col)))
     t0 = time.perf_counter()
-    orc.sy2sb(A, w, ncols=k)
+    run(k)
     dt = time.perf_counter() - t0
-    flops = sum(4.0 * (n - c - w) ** 2 for c in range(k))
+    if is_ge:
+        # step c: left reflector on an (m-c) x (n-c) block, right one on an
+        # (m-c-1) x (n-c-w) block, 4 flops per entry each
+        flops = sum(4.0 * (m - c) * (n - c) + 4.0 * (m - c - 1) * max(n - c - w, 0)
+                    for c in range(k))
+        what = f"first {k} of {n} steps of the {m} x {n}, w={w} matrix"
+    else:
+        flops = sum(4.0 * (n - c - w) ** 2 for c in range(k))
+        what = (f"first {k} of {n - w - 1} reflector columns of the n={n}, w={w} matrix "
+                f"(4 j^2 flops per column of trailing order j)")
     return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": orc.threads(), "kind": "oracle",
-            "sample": f"first {k} of {n - w - 1} reflector columns of the n={n}, w={w} matrix "
-                      f"(4 j^2 flops per column of trailing order j), {dt:.1f} s incl. the "
-                      f"oracle's full-matrix copy in and out"}
+            "sample": f"{what}, {dt:.1f} s incl. the oracle's full-matrix copy in and out"}
 
 
 def batch_bytes(ns, w, b):
-    """Algorithmic HBM bytes of the batched reduction: per panel of trailing
-    order j, the lower triangle of A2 is read by X = A2 Wt and read and
-    written by the rank-2b update (3 x 8 j^2 / 2 bytes), plus the panel read
-    and written once (16 j b bytes)."""
+    """Algorithmic HBM bytes of the batched reduction (w = b = 16 path): the
+    first panel's X pass reads the lower triangle of A2 once (8 j^2 / 2
+    bytes); every panel then reads and writes it once (8 j^2 bytes: the
+    update of this panel fused with the next panel's X), and the panel
+    itself is read and written once (16 j b bytes)."""
     tot = 0.0
     for n in ns:
+        first = True
         for c in range(0, max(n - w - 1, 0), b):
             j = n - c - w
-            tot += 12.0 * j * j + 16.0 * j * b
+            tot += (4.0 * j * j if first else 0.0) + 8.0 * j * j + 16.0 * j * b
+            first = False
     return tot
 
 
@@ -378,12 +392,18 @@ def main():
     torch.cuda.synchronize()
     prof_serial = br.bandred_profile_read()
     br.bandred_profile_enable(False)
-    dom = max((k for k in prof if prof[k]["flops"] > 0), key=lambda k: prof[k]["ms"])
-    d = prof[dom]
+    # the roofline entry is the contraction class with the most device time
+    # (serial step, every kernel alone); the panel classes, latency-bound
+    # single-workgroup and tall-skinny kernels, are listed in "kernels"
+    mfma_cls = ("symm", "syr2k", "gemm_update")
+    dom = max((k for k in prof_serial if k in mfma_cls and prof_serial[k]["launches"]),
+              key=lambda k: prof_serial[k]["ms"])
+    d = prof_serial[dom]
     achieved = d["flops"] / (d["ms"] / 1e3) / 1e12
     roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_TFLOPS["fp64"],
                 "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["fp64"], "traffic": None,
-                "avg_launch_ms": d["ms"] / max(d["launches"], 1), "launches": d["launches"]}
+                "avg_launch_ms": d["ms"] / max(d["launches"], 1), "launches": d["launches"],
+                "flops_per_launch": d["flops"] / max(d["launches"], 1)}
     breakdown = {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
                      "tflops": (v["flops"] / (v["ms"] / 1e3) / 1e12) if v["ms"] > 0 and v["flops"] > 0 else None}
                  for k, v in prof.items() if v["launches"]}
@@ -414,7 +434,7 @@ def main():
             forms[prec] = f
 
     cpu = None
-    if not args.no_cpu_baseline and not is_ge:
+    if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle, bounded sample)")
         cpu = cpu_baseline(p, A0)
 

@@ -158,7 +158,7 @@ __device__ __forceinline__ void stash(typename Stage<PREC>::T *lds, int part_str
 // ---------------------------------------------------------------------------
 
 template <int BM, int BN, int OPA, int OPB, int EPI, int PREC>
-__global__ __launch_bounds__(kThreads) void k_gemm(GemmDesc d) {
+__global__ __launch_bounds__(kThreads, 2) void k_gemm(GemmDesc d) {
   using T = typename Stage<PREC>::T;
   constexpr int NP = Stage<PREC>::NPARTS;
   constexpr int LDA_S = BM + 1;  // odd stride: transposed stores spread over banks
