@@ -182,8 +182,8 @@ def sy2sb(A, w: int, b: int | None = None, prec="fp64", lookahead: bool = True,
     return tau[: max(n - w, 0)]
 
 
-def ge2gb(A, w: int, b: int | None = None, prec="fp64", panel_rows: int = 0,
-          panel_method: int = 0, stream=None):
+def ge2gb(A, w: int, b: int | None = None, prec="fp64", lookahead: bool = True,
+          panel_rows: int = 0, panel_method: int = 0, stream=None):
     """Reduce the column-major CUDA tensor ``A`` (m >= n) to upper
     triangular-band width ``w`` in place; returns (tauq, taup)."""
     import torch
@@ -194,7 +194,7 @@ def ge2gb(A, w: int, b: int | None = None, prec="fp64", panel_rows: int = 0,
     tauq = torch.zeros(max(n, 1), dtype=torch.float64, device=A.device)
     taup = torch.zeros(max(n, 1), dtype=torch.float64, device=A.device)
     p = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
-    o = Opts(1, int(panel_rows), int(panel_method))
+    o = Opts(1 if lookahead else 0, int(panel_rows), int(panel_method))
     rc = bandred_ge2gb_ex(m, n, w, b, A.data_ptr(), lda, tauq.data_ptr(), taup.data_ptr(), p, o,
                           _stream_handle(stream))
     _check("bandred_ge2gb_ex", rc)

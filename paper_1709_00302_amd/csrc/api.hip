@@ -93,7 +93,7 @@ struct DevState {
   size_t bytes = 0;
   hipEvent_t done = nullptr;  // completion of the previous call's work
   hipStream_t aux = nullptr;  // look-ahead (panel) stream
-  hipEvent_t ev_a = nullptr, ev_b = nullptr;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr, ev_d = nullptr;
   int *flags = nullptr;       // [0] status, [1] abort   (device)
   long long timeout_ticks = 0;
   int num_cu = 0;
@@ -128,6 +128,8 @@ static int dev_state(DevState **out) {
     BR_HIP_CHECK(hipEventCreateWithFlags(&st.done, hipEventDisableTiming));
     BR_HIP_CHECK(hipEventCreateWithFlags(&st.ev_a, hipEventDisableTiming));
     BR_HIP_CHECK(hipEventCreateWithFlags(&st.ev_b, hipEventDisableTiming));
+    BR_HIP_CHECK(hipEventCreateWithFlags(&st.ev_c, hipEventDisableTiming));
+    BR_HIP_CHECK(hipEventCreateWithFlags(&st.ev_d, hipEventDisableTiming));
     BR_HIP_CHECK(hipStreamCreateWithFlags(&st.aux, hipStreamNonBlocking));
     BR_HIP_CHECK(hipMalloc((void **)&st.flags, 64));
     BR_HIP_CHECK(hipMemset(st.flags, 0, 64));
@@ -516,17 +518,20 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
   const int m = (int)m64, n = (int)n64, w = (int)w64, b = (int)b64;
   const int panel_rows = opts ? opts->panel_rows : 0;
   const int method = opts ? opts->panel_method : 0;
+  // look-ahead when the next left panel is the first column block of D (w = b)
+  const bool la = (opts ? opts->lookahead : 1) && w == b;
   DevState *st = nullptr;
   int rc = dev_state(&st);
   if (rc) return rc;
   const int npan = (n + b - 1) / b;
   const size_t part_cap = std::max<size_t>((size_t)8 * m * b, (size_t)256 * b * b);
+  const size_t part_pan = (size_t)(m / 256 + 2) * b * b;
   size_t need = 0;
   need += 2 * round_up((size_t)m * b * 8, 256);       // Vq, Wtq
   need += 2 * round_up((size_t)n * b * 8, 256);       // Up, Wtp
   need += round_up((size_t)b * n * 8, 256);           // Z (b x n)
   need += round_up((size_t)m * b * 8, 256);           // X (m x b)
-  need += round_up(part_cap * 8, 256);
+  need += round_up(part_cap * 8, 256) + round_up(part_pan * 8, 256);
   need += 2 * round_up((size_t)b * b * 8, 256);       // Tq, Tp
   need += PanelWs::bytes(m, b);
   need += 3 * round_up((size_t)(2 * npan + 2) * 4, 256);
@@ -540,12 +545,15 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
   double *Zb = ar.take<double>((size_t)b * n);
   double *Xb = ar.take<double>((size_t)m * b);
   double *part = ar.take<double>(part_cap);
+  double *partp = ar.take<double>(part_pan);
   double *Tq = ar.take<double>((size_t)b * b), *Tp = ar.take<double>((size_t)b * b);
   PanelWs pw;
   pw.carve(ar, m, b);
   unsigned *counters = ar.take<unsigned>(2 * npan + 2);
   int *pflags = ar.take<int>(2 * (2 * npan + 2));
   Ctx cx{st, s, part, part_cap};
+  hipStream_t ps = la ? st->aux : s;  // panel stream
+  Ctx cxp{st, ps, partp, part_pan};  // panels: their own split-k buffer on either stream
 
   BR_HIP_CHECK(hipStreamWaitEvent(s, st->done, 0));
   rc = launch_fill_u32(counters, 2 * npan + 2, 0u, s); if (rc) return rc;
@@ -554,41 +562,114 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
   rc = launch_fill(tauq, n, 0.0, s); if (rc) return rc;
   rc = launch_fill(taup, n, 0.0, s); if (rc) return rc;
 
+  // left panel `it` (columns c .. c+pb-1) and Wtq = Vq Tq, on stream q
+  auto left_panel = [&](int it, Ctx &c_, hipStream_t q) -> int {
+    const int c = it * b, pb = std::min(b, n - c), i = m - c;
+    int r = panel_factor(c_, false, A + c + (int64_t)c * lda, lda, i, pb, Vq, i, tauq + c, Tq, pb,
+                         pw, counters + 2 * it, pflags + 4 * it, method, panel_rows, q);
+    if (r) return r;
+    return gemm(c_, C_GEMM_SMALL, A_N, B_N, P_F64, i, pb, pb, Vq, i, Tq, pb, Wtq, i, 1.0, 0.0, q);
+  };
+  // right panel of step `it` (rows c .. c+pr-1 from column c+w) and Wtp = Up Tp
+  auto right_panel = [&](int it, Ctx &c_, hipStream_t q) -> int {
+    const int c = it * b, pb = std::min(b, n - c);
+    const int pr = std::max(0, std::min(pb, n - w - 1 - c));
+    const int c0 = c + w, jr = n - c0;
+    int r = panel_factor(c_, true, A + c + (int64_t)c0 * lda, lda, jr, pr, Up, jr, taup + c, Tp, pr,
+                         pw, counters + 2 * it + 1, pflags + 4 * it + 2, method, panel_rows, q);
+    if (r) return r;
+    return gemm(c_, C_GEMM_SMALL, A_N, B_N, P_F64, jr, pr, pr, Up, jr, Tp, pr, Wtp, jr, 1.0, 0.0, q);
+  };
+
+  // Per step (Sec. 3.1): (1) left QR, Wtq = Vq Tq; (2) E -= Vq (Wtq^T E);
+  // (3) right LQ of the updated top rows, Wtp = Up Tp; (4) D -= (D Wtp) Up^T.
+  // With look-ahead the panels run on the panel stream: (3) as soon as the
+  // top rows of E are updated (overlapping the rest of (2)), and the next
+  // step's (1) as soon as the first column block of D is updated
+  // (overlapping the rest of (4)).
+  if (la) {
+    BR_HIP_CHECK(hipEventRecord(st->ev_a, s));
+    BR_HIP_CHECK(hipStreamWaitEvent(ps, st->ev_a, 0));
+  }
+  rc = left_panel(0, cxp, ps);
+  if (rc) return rc;
+  if (la) {
+    BR_HIP_CHECK(hipEventRecord(st->ev_b, ps));
+    BR_HIP_CHECK(hipStreamWaitEvent(s, st->ev_b, 0));
+  }
   for (int it = 0, c = 0; c < n; ++it, c += b) {
     const int pb = std::min(b, n - c);
     const int i = m - c;
-    // (1) left panel QR of A[c:m, c:c+pb]; Wtq = Vq Tq
-    rc = panel_factor(cx, false, A + c + (int64_t)c * lda, lda, i, pb, Vq, i, tauq + c, Tq, pb, pw,
-                      counters + 2 * it, pflags + 4 * it, method, panel_rows, s);
-    if (rc) return rc;
-    rc = gemm(cx, C_GEMM_SMALL, A_N, B_N, P_F64, i, pb, pb, Vq, i, Tq, pb, Wtq, i, 1.0, 0.0, s);
-    if (rc) return rc;
-    // (2) E = A[c:m, c+pb:n] -= Vq (Wtq^T E)
+    const int pr = std::max(0, std::min(pb, n - w - 1 - c));
     const int ne = n - c - pb;
+    // (2) E = A[c:m, c+pb:n] -= Vq (Wtq^T E): top pr rows first
     if (ne > 0) {
       double *E = A + c + (int64_t)(c + pb) * lda;
       rc = gemm(cx, C_GEMM_UPD, A_T, B_N, prec, pb, ne, i, Wtq, i, E, lda, Zb, pb, 1.0, 0.0, s);
       if (rc) return rc;
-      rc = gemm(cx, C_GEMM_UPD, A_N, B_N, prec, i, ne, pb, Vq, i, Zb, pb, E, lda, -1.0, 1.0, s);
+      const int top = (la && pr > 0) ? pr : i;
+      rc = gemm(cx, C_GEMM_UPD, A_N, B_N, prec, top, ne, pb, Vq, i, Zb, pb, E, lda, -1.0, 1.0, s);
+      if (rc) return rc;
+      if (top < i) {
+        BR_HIP_CHECK(hipEventRecord(st->ev_c, s));
+        BR_HIP_CHECK(hipStreamWaitEvent(ps, st->ev_c, 0));
+        rc = right_panel(it, cxp, ps);  // (3) overlaps the rest of (2)
+        if (rc) return rc;
+        BR_HIP_CHECK(hipEventRecord(st->ev_d, ps));
+        rc = gemm(cx, C_GEMM_UPD, A_N, B_N, prec, i - top, ne, pb, Vq + top, i, Zb, pb,
+                  E + top, lda, -1.0, 1.0, s);
+        if (rc) return rc;
+        BR_HIP_CHECK(hipStreamWaitEvent(s, st->ev_d, 0));
+      } else if (pr > 0) {
+        rc = right_panel(it, cxp, s);
+        if (rc) return rc;
+      }
+    } else if (pr > 0) {
+      rc = right_panel(it, cxp, s);
       if (rc) return rc;
     }
-    // (3) right LQ of the rows c .. c+pr-1 that own a right reflector; Wtp = U Tp
-    const int pr = std::max(0, std::min(pb, n - w - 1 - c));
+    const bool next = (c + pb < n);
     if (pr > 0) {
+      // (4) D = A[c+pr:m, c0:n] -= (D Wtp) Up^T
       const int c0 = c + w, jr = n - c0;
-      rc = panel_factor(cx, true, A + c + (int64_t)c0 * lda, lda, jr, pr, Up, jr, taup + c, Tp, pr,
-                        pw, counters + 2 * it + 1, pflags + 4 * it + 2, method, panel_rows, s);
-      if (rc) return rc;
-      rc = gemm(cx, C_GEMM_SMALL, A_N, B_N, P_F64, jr, pr, pr, Up, jr, Tp, pr, Wtp, jr, 1.0, 0.0, s);
-      if (rc) return rc;
-      // (4) D = A[c+pr:m, c0:n] -= (D Wtp) U^T
       const int md = m - c - pr;
       if (md > 0) {
         double *D = A + (c + pr) + (int64_t)c0 * lda;
         rc = gemm(cx, C_GEMM_UPD, A_N, B_N, prec, md, pr, jr, D, lda, Wtp, jr, Xb, md, 1.0, 0.0, s);
         if (rc) return rc;
+        // with w = b and pr = pb the next left panel is D's first column block
+        const int lcols = (la && next && pr == pb) ? std::min(b, jr) : 0;
+        if (lcols > 0) {
+          rc = gemm(cx, C_GEMM_UPD, A_N, B_T, prec, md, lcols, pr, Xb, md, Up, jr, D, lda, -1.0,
+                    1.0, s);
+          if (rc) return rc;
+          BR_HIP_CHECK(hipEventRecord(st->ev_a, s));
+          BR_HIP_CHECK(hipStreamWaitEvent(ps, st->ev_a, 0));
+          rc = left_panel(it + 1, cxp, ps);  // next (1) overlaps the rest of (4)
+          if (rc) return rc;
+          BR_HIP_CHECK(hipEventRecord(st->ev_b, ps));
+          if (jr > lcols) {
+            rc = gemm(cx, C_GEMM_UPD, A_N, B_T, prec, md, jr - lcols, pr, Xb, md, Up + lcols, jr,
+                      D + (int64_t)lcols * lda, lda, -1.0, 1.0, s);
+            if (rc) return rc;
+          }
+          BR_HIP_CHECK(hipStreamWaitEvent(s, st->ev_b, 0));
+          continue;
+        }
         rc = gemm(cx, C_GEMM_UPD, A_N, B_T, prec, md, jr, pr, Xb, md, Up, jr, D, lda, -1.0, 1.0, s);
         if (rc) return rc;
+      }
+    }
+    if (next) {
+      if (la) {
+        BR_HIP_CHECK(hipEventRecord(st->ev_a, s));
+        BR_HIP_CHECK(hipStreamWaitEvent(ps, st->ev_a, 0));
+      }
+      rc = left_panel(it + 1, cxp, ps);
+      if (rc) return rc;
+      if (la) {
+        BR_HIP_CHECK(hipEventRecord(st->ev_b, ps));
+        BR_HIP_CHECK(hipStreamWaitEvent(s, st->ev_b, 0));
       }
     }
   }

@@ -53,3 +53,19 @@ def test_ge2gb_banded_input_is_exact(bandred):
     Ag, tqg, tpg = _run(bandred, A, w, w)
     assert np.all(tqg == 0.0) and np.all(tpg == 0.0)
     assert np.array_equal(Ag, A)
+
+
+@pytest.mark.parametrize("m,n,w", [(1200, 900, 64), (700, 700, 32), (1000, 1000, 128)])
+def test_ge2gb_lookahead_is_bit_identical_to_serial(bandred, m, n, w):
+    """The look-ahead only reorders independent launches (panels on the
+    second stream, updates split by rows or columns with the same k order)."""
+    print(f"case ge2gb lookahead m={m} n={n} w={w}", flush=True)
+    A = inputs.ge_normal(m, n, 500 + w)
+    outs = []
+    for la in (True, False):
+        Ad, _ = to_device_colmajor(A)
+        tq, tp = bandred.ge2gb(Ad, w, w, lookahead=la)
+        torch.cuda.synchronize()
+        outs.append((Ad.cpu().numpy(), tq.cpu().numpy(), tp.cpu().numpy()))
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y)
