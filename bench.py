@@ -44,6 +44,28 @@ def nominal_flops(p):
     return 4.0 * n ** 3 / 3.0  # Sec. 2.1
 
 
+def pmc_traffic(cls, workload):
+    """HBM bytes per launch of the SYR2K kernel from the committed PMC
+    summary (FETCH_SIZE and WRITE_SIZE runs, calibrated on a plain copy);
+    None unless the summary covers this kernel and workload and the GEMM
+    source is unchanged since the counters were taken."""
+    import hashlib
+    import re
+
+    if cls != "syr2k" or workload != "sy2sb_n16384_w128":
+        return None
+    path = os.path.join(ROOT, "profiles", "syr2k_n16384_w128_pmc_traffic.md")
+    src = os.path.join(ROOT, "paper_1709_00302_amd", "csrc", "gemm.hip")
+    try:
+        txt = open(path).read()
+        val = float(re.search(r"syr2k_traffic_bytes_per_launch:\s*([0-9.eE+-]+)", txt).group(1))
+        sha = re.search(r"gemm.hip sha256 prefix at measurement:\s*([0-9a-f]+)", txt).group(1)
+    except (OSError, AttributeError, ValueError):
+        return None
+    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    return val if cur.startswith(sha) else None
+
+
 def time_steps(run, restore, steps, stream):
     import torch
 
@@ -401,7 +423,8 @@ def main():
     d = prof_serial[dom]
     achieved = d["flops"] / (d["ms"] / 1e3) / 1e12
     roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_TFLOPS["fp64"],
-                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["fp64"], "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["fp64"],
+                "traffic": pmc_traffic(dom, args.workload),
                 "avg_launch_ms": d["ms"] / max(d["launches"], 1), "launches": d["launches"],
                 "flops_per_launch": d["flops"] / max(d["launches"], 1)}
     breakdown = {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
