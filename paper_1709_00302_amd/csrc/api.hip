@@ -345,7 +345,7 @@ static int panel_factor(Ctx &cx, bool rowmajor, double *P, int64_t ldp, int m, i
   if (rc) return rc;
   {
     ProfScope p2(C_PANEL_SMALL, 0.0, s);
-    rc = launch_recon(pw.Qtop, nb, nb, V, ldv, T, ldt, tau, pw.Ui, pw.sgn, flag, s);
+    rc = launch_recon(pw.Qtop, nb, nb, V, ldv, T, ldt, tau, pw.Ui, pw.sgn, pw.piv, flag, s);
     if (rc) return rc;
   }
   // M = R2^-1 U^-1 ; Rh0 = R2 R1 ; V(nb:m, :) = Q1(nb:m, :) M ; write in place

@@ -14,18 +14,19 @@
 // stored reflectors and tau are those of the unblocked reduction.  The
 // bottom rows are formed as V(b:m, :) = Q1(b:m, :) (R2^-1 U^-1).
 //
-// The O(m b^2) products run on the MFMA GEMM kernel; the O(b^3) sequential
-// factorisations run here in one workgroup of 1024 threads.  Each thread keeps
-// a 4 x 4 tile of the b x b matrix in registers (32 x 32 tiles cover
-// b = 128; sizes below 128 are padded with the identity, which every
-// operation below leaves invariant).  The factorisations are blocked by 4 and
-// take one workgroup barrier per block step: the diagonal block and its block
-// row are handled by the wave that owns them (broadcasts from the diagonal
-// tile's lane through the scalar unit), the block row and column are
-// published through LDS, and every trailing tile takes one rank-4 update.
-// What other threads need of a diagonal block is either fixed in advance
-// (diagonal blocks of a triangular matrix, stored once) or recomputed by each
-// thread from the published raw block.
+// The O(m b^2) products run on the MFMA GEMM kernel.  The two sequential
+// O(b^3) factorisations (Cholesky, LU) run in one workgroup of 1024 threads:
+// each thread keeps a 4 x 4 tile of the b x b matrix in registers (32 x 32
+// tiles cover b = 128; sizes below 128 are padded with the identity, which
+// every operation below leaves invariant).  They are blocked by 4 and take one
+// workgroup barrier per block step: the diagonal block and its block row are
+// handled by the wave that owns them (broadcasts from the diagonal tile's
+// lane), the block row and column are published through LDS, and every
+// trailing tile takes one rank-4 update.  What other threads need of a
+// diagonal block is either fixed in advance or recomputed by each thread from
+// the published raw block.  The triangular inverses (R1^-1, R2^-1, U^-1) and
+// the solve for T are independent column by column (row by row for T), so they
+// run on one workgroup per 16-wide slab with the triangular operand in LDS.
 //
 // Rank-deficient or structurally reduced panels: a pivot of the first
 // Cholesky below rel * (original diagonal), or a panel with no nonzero below
@@ -88,17 +89,20 @@ __device__ __forceinline__ double rsq_nr(double x) {
 
 // Shared buffers of the blocked steps (double buffered by block parity).
 // The block row / column buffers double as the staging area of coalesced
-// tile loads and stores (32 columns of 128 rows at a time).
+// tile loads and stores (32 columns of 128 rows at a time, column stride
+// kLdStage: with an odd stride the tiles' 4-row pieces of different columns
+// fall in different LDS banks).
+constexpr int kLdStage = kNbMax + 1;
 struct Bcast {
   union {
     struct {
-      double rb[2][kTE][kNbMax];  // a block row (4 rows)
+      double rb[2][kTE][kTE][kNTl];  // a block row: rb[.][r][q][J] = row r, column 4 J + q
       double cb[2][kNbMax][kTE];  // a block column (4 columns)
     };
-    double stage[32 * kNbMax];
+    double stage[32 * kLdStage];
   };
-  double dg[kNTl][kTE * kTE];   // per-block data fixed during a sweep
   double pb[2][kTE * kTE];      // the current diagonal block
+  double pr[2][kTE];            // reciprocals of its pivots
   double d0[kNbMax];            // original diagonal (Cholesky breakdown test)
   double sg[kNbMax];            // LU signs
   int bad;
@@ -117,49 +121,84 @@ __device__ __forceinline__ void tile_load(Tile &T, const TileCtx &c, Bcast &s, c
     for (int k = 0; k < E; ++k) {
       const int e = c.t + kRT * k;
       const int i = e & (kNbMax - 1), j = 32 * ch + (e >> 7);
-      v[ch][k] = (i < b && j < b) ? G[i + (int64_t)j * ld] : (i == j ? 1.0 : 0.0);
+      const bool in = i < b && j < b;
+      const double x = G[in ? i + (int64_t)j * ld : 0];  // clamped: no branch, no wait
+      v[ch][k] = in ? x : (i == j ? 1.0 : 0.0);
     }
 #pragma unroll
   for (int ch = 0; ch < 4; ++ch) {
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < E; ++k) s.stage[c.t + kRT * k] = v[ch][k];
+    for (int k = 0; k < E; ++k) {
+      const int e = c.t + kRT * k;
+      s.stage[(e >> 7) * kLdStage + (e & (kNbMax - 1))] = v[ch][k];
+    }
     __syncthreads();
     if ((c.bj >> 3) == ch) {
       const int j0 = kTE * (c.bj & 7);
 #pragma unroll
       for (int r = 0; r < kTE; ++r)
 #pragma unroll
-        for (int q = 0; q < kTE; ++q) T.a[r][q] = s.stage[(j0 + q) * kNbMax + kTE * c.bi + r];
+        for (int q = 0; q < kTE; ++q) T.a[r][q] = s.stage[(j0 + q) * kLdStage + kTE * c.bi + r];
     }
   }
   __syncthreads();
 }
 
-// store (parts of) the tile straight from the registers: mode 0 all, 1 upper
-// (zeros below), 2 unit lower (ones on the diagonal, zeros above)
-__device__ __forceinline__ void tile_store(const Tile &T, const TileCtx &c, Bcast &, double *G,
+// store (parts of) the tile: mode 0 all, 1 upper (zeros below), 2 unit lower
+// (ones on the diagonal, zeros above).  The tiles are regrouped through LDS 32
+// columns at a time so that every global store is a contiguous column run.
+__device__ __forceinline__ void tile_store(const Tile &T, const TileCtx &c, Bcast &s, double *G,
                                            int64_t ld, int b, int mode) {
+  constexpr int E = 32 * kNbMax / kRT;
 #pragma unroll
-  for (int q = 0; q < kTE; ++q)
+  for (int ch = 0; ch < 4; ++ch) {
+    if (32 * ch >= b) break;
+    __syncthreads();
+    if ((c.bj >> 3) == ch) {
+      const int j0 = kTE * (c.bj & 7);
 #pragma unroll
-    for (int r = 0; r < kTE; ++r) {
-      const int i = kTE * c.bi + r, j = kTE * c.bj + q;
-      double v = T.a[r][q];
-      if (mode == 1 && j < i) v = 0.0;
-      if (mode == 2) v = (i == j) ? 1.0 : (i > j ? v : 0.0);
-      if (i < b && j < b) G[i + (int64_t)j * ld] = v;
+      for (int r = 0; r < kTE; ++r)
+#pragma unroll
+        for (int q = 0; q < kTE; ++q) {
+          const int i = kTE * c.bi + r, j = kTE * c.bj + q;
+          double v = T.a[r][q];
+          if (mode == 1 && j < i) v = 0.0;
+          if (mode == 2) v = (i == j) ? 1.0 : (i > j ? v : 0.0);
+          s.stage[(j0 + q) * kLdStage + kTE * c.bi + r] = v;
+        }
     }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int e = c.t + kRT * k;
+      const int i = e & (kNbMax - 1), j = 32 * ch + (e >> 7);
+      if (i < b && j < b) G[i + (int64_t)j * ld] = s.stage[(e >> 7) * kLdStage + i];
+    }
+  }
+  __syncthreads();
+}
+
+// The wave that factors block row kb + 1 is on the critical path of step kb:
+// it runs at raised priority from the barrier of step kb until it has
+// published that row, so that its own trailing update is not slowed down by
+// the other waves of its SIMD.
+__device__ __forceinline__ void prio_next(const TileCtx &c, int kb) {
+  if ((c.t >> 6) == ((kb + 1) >> 1)) __builtin_amdgcn_s_setprio(3);
+  else __builtin_amdgcn_s_setprio(0);
 }
 
 // Blocked upper Cholesky in place: G = R^T R, R in the upper triangle.  The
 // block row kb is factored by its owners (one wave) with the diagonal tile's
 // values broadcast from its lane; the trailing upper tiles then take one
-// rank-4 update.  Returns false (in every thread) on a pivot <= rel * d0[k].
+// rank-4 update.  Returns false (in every thread) on a pivot <= rel * d0[k]
+// (s.d0 holds the original diagonal); the factorisation runs to the end
+// either way (a breakdown pivot is replaced by 1) and is checked once.
 __device__ __forceinline__ bool blk_chol(Tile &T, const TileCtx &c, Bcast &s, int b, double rel) {
   if (c.t == 0) s.bad = 0;
   __syncthreads();
   const int nblk = (b + kTE - 1) / kTE;
+  prio_next(c, -1);
   for (int kb = 0; kb < nblk; ++kb) {
     const int buf = kb & 1;
     if (c.bi == kb && c.bj >= kb) {
@@ -186,19 +225,19 @@ __device__ __forceinline__ bool blk_chol(Tile &T, const TileCtx &c, Bcast &s, in
 #pragma unroll
       for (int kr = 0; kr < kTE; ++kr)
 #pragma unroll
-        for (int q = 0; q < kTE; ++q) s.rb[buf][kr][kTE * c.bj + q] = T.a[kr][q];
+        for (int q = 0; q < kTE; ++q) s.rb[buf][kr][q][c.bj] = T.a[kr][q];
       if (diag && !ok) s.bad = 1;
     }
     __syncthreads();
-    if (s.bad) return false;
+    prio_next(c, kb);
     if (c.bi > kb && c.bj >= c.bi) {
 #pragma unroll
       for (int l = 0; l < kTE; ++l) {
         double x[kTE], y[kTE];
 #pragma unroll
-        for (int r = 0; r < kTE; ++r) x[r] = s.rb[buf][l][kTE * c.bi + r];
+        for (int r = 0; r < kTE; ++r) x[r] = s.rb[buf][l][r][c.bi];
 #pragma unroll
-        for (int q = 0; q < kTE; ++q) y[q] = s.rb[buf][l][kTE * c.bj + q];
+        for (int q = 0; q < kTE; ++q) y[q] = s.rb[buf][l][q][c.bj];
 #pragma unroll
         for (int r = 0; r < kTE; ++r)
 #pragma unroll
@@ -206,8 +245,9 @@ __device__ __forceinline__ bool blk_chol(Tile &T, const TileCtx &c, Bcast &s, in
       }
     }
   }
+  __builtin_amdgcn_s_setprio(0);
   __syncthreads();
-  return true;
+  return s.bad == 0;
 }
 
 // In-place inverse of the 4 x 4 upper triangular block a (zeros below).
@@ -228,77 +268,6 @@ __device__ __forceinline__ void inv4_upper(double (&a)[kTE][kTE]) {
   }
 }
 
-// Blocked in-place Gauss-Jordan inverse of an upper triangular matrix.
-// Pivot block kb: A_kk <- A_kk^-1, A_kj <- A_kk^-1 A_kj, A_ik <- -A_ik A_kk^-1
-// and A_ij -= A_ik(old) A_kj(new) for i < k < j.  A diagonal block is never
-// touched before its own step, so all the A_kk^-1 are formed up front (by the
-// diagonal owners, into LDS) and each step needs a single barrier.
-__device__ __forceinline__ void blk_inv_upper(Tile &T, const TileCtx &c, Bcast &s, int b) {
-  const int nblk = (b + kTE - 1) / kTE;
-  if (c.bi == c.bj) {
-    inv4_upper(T.a);
-#pragma unroll
-    for (int r = 0; r < kTE; ++r)
-#pragma unroll
-      for (int q = 0; q < kTE; ++q) s.dg[c.bi][kTE * r + q] = T.a[r][q];
-  }
-  __syncthreads();
-  for (int kb = 0; kb < nblk; ++kb) {
-    const int buf = kb & 1;
-    double P[kTE * kTE];
-    if ((c.bi == kb && c.bj > kb) || (c.bj == kb && c.bi < kb)) {
-#pragma unroll
-      for (int e = 0; e < kTE * kTE; ++e) P[e] = s.dg[kb][e];
-    }
-    if (c.bi == kb && c.bj > kb) {  // A_kj <- P A_kj, rows top-down in place
-#pragma unroll
-      for (int r = 0; r < kTE; ++r)
-#pragma unroll
-        for (int q = 0; q < kTE; ++q) {
-          double acc = 0.0;
-#pragma unroll
-          for (int l = r; l < kTE; ++l) acc += P[kTE * r + l] * T.a[l][q];
-          T.a[r][q] = acc;
-        }
-#pragma unroll
-      for (int r = 0; r < kTE; ++r)
-#pragma unroll
-        for (int q = 0; q < kTE; ++q) s.rb[buf][r][kTE * c.bj + q] = T.a[r][q];
-    }
-    if (c.bj == kb && c.bi < kb) {  // publish A_ik(old); A_ik <- -A_ik P
-#pragma unroll
-      for (int r = 0; r < kTE; ++r)
-#pragma unroll
-        for (int q = 0; q < kTE; ++q) s.cb[buf][kTE * c.bi + r][q] = T.a[r][q];
-#pragma unroll
-      for (int q = kTE - 1; q >= 0; --q)
-#pragma unroll
-        for (int r = 0; r < kTE; ++r) {
-          double acc = 0.0;
-#pragma unroll
-          for (int l = 0; l <= q; ++l) acc += T.a[r][l] * P[kTE * l + q];
-          T.a[r][q] = -acc;
-        }
-    }
-    __syncthreads();
-    if (c.bi < kb && c.bj > kb) {
-#pragma unroll
-      for (int l = 0; l < kTE; ++l) {
-        double x[kTE], y[kTE];
-#pragma unroll
-        for (int r = 0; r < kTE; ++r) x[r] = s.cb[buf][kTE * c.bi + r][l];
-#pragma unroll
-        for (int q = 0; q < kTE; ++q) y[q] = s.rb[buf][l][kTE * c.bj + q];
-#pragma unroll
-        for (int r = 0; r < kTE; ++r)
-#pragma unroll
-          for (int q = 0; q < kTE; ++q) T.a[r][q] -= x[r] * y[q];
-      }
-    }
-  }
-  __syncthreads();
-}
-
 // Blocked LU without pivoting of (W - S), S_k = -sign of the current pivot
 // (chosen on the fly).  L (unit, strict lower) and U (upper) overwrite the
 // tiles; the signs go to s.sg.  Step kb: the block row (diagonal LU and
@@ -307,6 +276,7 @@ __device__ __forceinline__ void blk_inv_upper(Tile &T, const TileCtx &c, Bcast &
 // L_ik = A_ik U_kk^-1 itself and applies the rank-4 update.
 __device__ __forceinline__ void blk_lu_sign(Tile &T, const TileCtx &c, Bcast &s, int b) {
   const int nblk = (b + kTE - 1) / kTE;
+  prio_next(c, -1);
   for (int kb = 0; kb < nblk; ++kb) {
     const int buf = kb & 1;
     if (c.bi == kb && c.bj >= kb) {
@@ -322,7 +292,10 @@ __device__ __forceinline__ void blk_lu_sign(Tile &T, const TileCtx &c, Bcast &s,
           T.a[kr][kr] = piv;
 #pragma unroll
           for (int i = kr + 1; i < kTE; ++i) T.a[i][kr] *= ip;
-          if (c.lane == dl) s.sg[kTE * kb + kr] = sgn;
+          if (c.lane == dl) {
+            s.sg[kTE * kb + kr] = sgn;
+            s.pr[buf][kr] = ip;
+          }
         }
 #pragma unroll
         for (int i = kr + 1; i < kTE; ++i) {
@@ -341,7 +314,7 @@ __device__ __forceinline__ void blk_lu_sign(Tile &T, const TileCtx &c, Bcast &s,
 #pragma unroll
         for (int r = 0; r < kTE; ++r)
 #pragma unroll
-          for (int q = 0; q < kTE; ++q) s.rb[buf][r][kTE * c.bj + q] = T.a[r][q];
+          for (int q = 0; q < kTE; ++q) s.rb[buf][r][q][c.bj] = T.a[r][q];
       }
     }
     if (c.bj == kb && c.bi > kb) {
@@ -351,6 +324,7 @@ __device__ __forceinline__ void blk_lu_sign(Tile &T, const TileCtx &c, Bcast &s,
         for (int q = 0; q < kTE; ++q) s.cb[buf][kTE * c.bi + r][q] = T.a[r][q];
     }
     __syncthreads();
+    prio_next(c, kb);
     if (c.bi > kb && c.bj >= kb) {
       // L_ik = A_ik U_kk^-1 from the published raw block
       double U[kTE * kTE], A[kTE][kTE];
@@ -363,7 +337,7 @@ __device__ __forceinline__ void blk_lu_sign(Tile &T, const TileCtx &c, Bcast &s,
       double L[kTE][kTE];
 #pragma unroll
       for (int q = 0; q < kTE; ++q) {
-        const double iu = rcp_nr(U[kTE * q + q]);
+        const double iu = s.pr[buf][q];
 #pragma unroll
         for (int r = 0; r < kTE; ++r) {
           double v = A[r][q];
@@ -382,7 +356,7 @@ __device__ __forceinline__ void blk_lu_sign(Tile &T, const TileCtx &c, Bcast &s,
         for (int l = 0; l < kTE; ++l) {
           double y[kTE];
 #pragma unroll
-          for (int q = 0; q < kTE; ++q) y[q] = s.rb[buf][l][kTE * c.bj + q];
+          for (int q = 0; q < kTE; ++q) y[q] = s.rb[buf][l][q][c.bj];
 #pragma unroll
           for (int r = 0; r < kTE; ++r)
 #pragma unroll
@@ -394,143 +368,296 @@ __device__ __forceinline__ void blk_lu_sign(Tile &T, const TileCtx &c, Bcast &s,
   __syncthreads();
 }
 
-// With L (strict lower, unit) and U (upper) in the tiles: T L^T = -U S,
-// solved in place over the upper triangle (L is kept), one column block of T
-// at a time.  The diagonal blocks of L are stored once; step lb solves the
-// column block lb of T against L_ll, publishes it with the L blocks of the
-// same block column, and the trailing upper tiles take one rank-4 update.
-__device__ __forceinline__ void blk_tsolve(Tile &T, const TileCtx &c, Bcast &s, int b) {
-#pragma unroll
-  for (int r = 0; r < kTE; ++r)
-#pragma unroll
-    for (int q = 0; q < kTE; ++q) {
-      const int i = kTE * c.bi + r, j = kTE * c.bj + q;
-      if (j >= i && j < b) T.a[r][q] = -T.a[r][q] * s.sg[j];
-    }
-  if (c.bi == c.bj) {
-#pragma unroll
-    for (int r = 0; r < kTE; ++r)
-#pragma unroll
-      for (int q = 0; q < kTE; ++q) s.dg[c.bi][kTE * r + q] = T.a[r][q];  // L_ll below the diagonal
-  }
-  __syncthreads();
-  const int nblk = (b + kTE - 1) / kTE;
-  for (int lb = 0; lb < nblk; ++lb) {
-    const int buf = lb & 1;
-    if (c.bj == lb) {
-      if (c.bi <= lb) {  // T_il = C_il L_ll^-T (upper part only on the diagonal tile)
-        double Ld[kTE * kTE];
-#pragma unroll
-        for (int e = 0; e < kTE * kTE; ++e) Ld[e] = s.dg[lb][e];
-        const bool diag = (c.bi == lb);
-#pragma unroll
-        for (int q = 0; q < kTE; ++q)
-#pragma unroll
-          for (int r = 0; r < kTE; ++r) {
-            if (diag && r > q) continue;
-            double v = T.a[r][q];
-#pragma unroll
-            for (int l = 0; l < q; ++l)
-              if (!diag || l >= r) v -= T.a[r][l] * Ld[kTE * q + l];
-            T.a[r][q] = v;
-          }
-#pragma unroll
-        for (int r = 0; r < kTE; ++r)
-#pragma unroll
-          for (int q = 0; q < kTE; ++q)
-            s.cb[buf][kTE * c.bi + r][q] = (diag && r > q) ? 0.0 : T.a[r][q];
-      } else {  // L_jl below the diagonal block
-#pragma unroll
-        for (int r = 0; r < kTE; ++r)
-#pragma unroll
-          for (int q = 0; q < kTE; ++q) s.cb[buf][kTE * c.bi + r][q] = T.a[r][q];
-      }
-    }
-    __syncthreads();
-    if (c.bi <= lb && c.bj > lb) {
-      // C_ij -= sum_l T(i, l) L(j, l) over the 4 columns l of block lb
-#pragma unroll
-      for (int l = 0; l < kTE; ++l) {
-        double x[kTE], y[kTE];
-#pragma unroll
-        for (int r = 0; r < kTE; ++r) x[r] = s.cb[buf][kTE * c.bi + r][l];
-#pragma unroll
-        for (int q = 0; q < kTE; ++q) y[q] = s.cb[buf][kTE * c.bj + q][l];
-#pragma unroll
-        for (int r = 0; r < kTE; ++r)
-#pragma unroll
-          for (int q = 0; q < kTE; ++q) T.a[r][q] -= x[r] * y[q];
-      }
-    }
-  }
-  __syncthreads();
-}
-
 // ---------------------------------------------------------------------------
-// kernel A: R = chol(G), R^-1 (both full column-major, zeros below)
+// kernel A: R = chol(G) (full column-major, zeros below); R^-1 follows in
+// k_trinv
 // flag[0]: raised on breakdown; flag[1]: nonzero count of the panel's
 // strictly lower part (0 = structurally reduced panel)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kRT) void k_chol_inv(const double *G, int ldg, int b, double rel,
-                                                  double *R, double *Rinv, int *flag,
-                                                  int check_structure) {
+__global__ __launch_bounds__(kRT) void k_chol(const double *G, int ldg, int b, double rel,
+                                              double *R, int *flag, int check_structure) {
   __shared__ Bcast s;
-  if (flag[0]) return;
-  if (check_structure && flag[1] == 0) {
+  // the flags are read before, and tested after, the matrix loads so that the
+  // two memory latencies overlap
+  const int f0 = flag[0], f1 = flag[1];
+  const TileCtx c = tile_ctx();
+  Tile T;
+  tile_load(T, c, s, G, ldg, b);
+  if (f0) return;
+  if (check_structure && f1 == 0) {
     if (threadIdx.x == 0) flag[0] = 1;
     return;
   }
-  const TileCtx c = tile_ctx();
-  if (c.t < kNbMax) s.d0[c.t] = (c.t < b) ? G[c.t + (int64_t)c.t * ldg] : 1.0;
-  Tile T;
-  tile_load(T, c, s, G, ldg, b);
-  __syncthreads();
+  if (c.bi == c.bj) {
+#pragma unroll
+    for (int r = 0; r < kTE; ++r) s.d0[kTE * c.bi + r] = T.a[r][r];  // identity pad beyond b
+  }
   if (!blk_chol(T, c, s, b, rel)) {
     if (c.t == 0) flag[0] = 1;
     return;
   }
-  // the upper factor only: zero the strictly lower tiles and parts
-#pragma unroll
-  for (int r = 0; r < kTE; ++r)
-#pragma unroll
-    for (int q = 0; q < kTE; ++q)
-      if (kTE * c.bj + q < kTE * c.bi + r) T.a[r][q] = 0.0;
-  tile_store(T, c, s, R, b, b, 1);
-  blk_inv_upper(T, c, s, b);
-  tile_store(T, c, s, Rinv, b, b, 1);
+  tile_store(T, c, s, R, b, b, 1);  // upper factor, zeros below
 }
 
 // ---------------------------------------------------------------------------
-// kernel B: Qtop (b x b) -> LU with signs -> V top block (unit lower),
-// T = -U S L^-T (and tau), U^-1 (full, zeros below), S
+// kernel B: Qtop (b x b) -> LU with signs: L (unit lower) into V's top block,
+// U into a scratch (upper, zeros below), the signs into sgn
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kRT) void k_recon(const double *Qtop, int ldq, int b, double *V,
-                                               int64_t ldv, double *Tout, int ldt, double *tau,
-                                               double *Uinv, double *sgn, const int *flag) {
+__global__ __launch_bounds__(kRT) void k_lu(const double *Qtop, int ldq, int b, double *V,
+                                            int64_t ldv, double *U, double *sgn, const int *flag) {
   __shared__ Bcast s;
-  if (flag[0]) return;
+  const int f0 = flag[0];
   const TileCtx c = tile_ctx();
   Tile T;
   tile_load(T, c, s, Qtop, ldq, b);
-  __syncthreads();
+  if (f0) return;
   blk_lu_sign(T, c, s, b);
-  tile_store(T, c, s, V, ldv, b, 2);     // L -> V(0:b, :)
-  tile_store(T, c, s, Uinv, b, b, 1);    // U kept in global memory for its inverse
-  blk_tsolve(T, c, s, b);
-  tile_store(T, c, s, Tout, ldt, b, 1);
-#pragma unroll
-  for (int r = 0; r < kTE; ++r)
-#pragma unroll
-    for (int q = 0; q < kTE; ++q) {
-      const int i = kTE * c.bi + r, j = kTE * c.bj + q;
-      if (i == j && i < b) tau[i] = T.a[r][q];
-    }
+  tile_store(T, c, s, V, ldv, b, 2);  // L -> V(0:b, :)
+  tile_store(T, c, s, U, b, b, 1);
   if (c.t < b) sgn[c.t] = s.sg[c.t];
+}
+
+// ---------------------------------------------------------------------------
+// Column- and row-independent triangular solves, one 16-wide slab per
+// workgroup of 256 threads (thread t: slab column or row t % 16, the other
+// index t / 16 + 16 k for k = 0..7), blocked by 4 with the 4 x 4 diagonal
+// pieces fixed in advance; the b x b operand sits in LDS.
+// ---------------------------------------------------------------------------
+constexpr int kST = 256;           // threads of a slab workgroup
+constexpr int kSW = 16;            // slab width
+constexpr int kLdS = kNbMax + 1;   // LDS row stride of the b x b operand
+
+struct SlabLds {
+  double M[kNbMax * kLdS];         // the triangular operand, M[i * kLdS + j] = op(i, j)
+  double dg[kNbMax / 4][16];       // inverses of the 4 x 4 diagonal blocks
+  double xb[2][4][kSW];            // the current 4-row (or 4-column) block, by parity
+};
+
+// M(i, j) = G(i, j) for columns c0 <= j < c1 and all 128 rows, from the
+// column-major b x b matrix G; outside b x b (and, for STRICT_LOWER, on and
+// above the diagonal) the identity (zero for STRICT_LOWER).  Loads go out in
+// batches of kLB per thread before any is written, with clamped addresses
+// instead of branches so that nothing waits between them.
+template <bool STRICT_LOWER>
+__device__ __forceinline__ void slab_load(SlabLds &L, const double *G, int64_t ld, int b, int c0,
+                                          int c1) {
+  constexpr int kLB = 16;
+  // (c1 - c0) is even, so every thread has the same count of elements; the
+  // last batch repeats the thread's last element instead of branching
+  const int nper = (c1 - c0) * kNbMax / kST;
+  for (int u0 = 0; u0 < nper; u0 += kLB) {
+    double v[kLB];
+#pragma unroll
+    for (int u = 0; u < kLB; ++u) {
+      const int e = (int)threadIdx.x + kST * min(u0 + u, nper - 1);
+      const int i = e & (kNbMax - 1), j = c0 + (e >> 7);
+      const bool in = i < b && j < b && (!STRICT_LOWER || i > j);
+      v[u] = G[in ? i + (int64_t)j * ld : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < kLB; ++u) {
+      const int e = (int)threadIdx.x + kST * min(u0 + u, nper - 1);
+      const int i = e & (kNbMax - 1), j = c0 + (e >> 7);
+      const bool in = i < b && j < b && (!STRICT_LOWER || i > j);
+      L.M[i * kLdS + j] = in ? v[u] : ((!STRICT_LOWER && i == j) ? 1.0 : 0.0);
+    }
+  }
+}
+
+// M(r, 4 i4 + q), q < 4, for the rows r = g + 16 k with k <= i4 / 4 (the rows
+// at or above block i4; others are left untouched).  i4 is a constant after
+// unrolling.
+__device__ __forceinline__ void slab_fetch_above(const SlabLds &L, int g, int i4,
+                                                 double (&m)[8][4]) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (k <= (i4 >> 2))
+#pragma unroll
+      for (int q = 0; q < 4; ++q) m[k][q] = L.M[(g + 16 * k) * kLdS + 4 * i4 + q];
+}
+
+// M(r, 4 j4 + q), q < 4, for the rows r = g + 16 k with k >= j4 / 4.
+__device__ __forceinline__ void slab_fetch_below(const SlabLds &L, int g, int j4,
+                                                 double (&m)[8][4]) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (k >= (j4 >> 2))
+#pragma unroll
+      for (int q = 0; q < 4; ++q) m[k][q] = L.M[(g + 16 * k) * kLdS + 4 * j4 + q];
+}
+
+// X = R^-1 for the upper triangular R (columns 16J .. 16J+15 in workgroup J).
+__device__ __forceinline__ void slab_trinv(SlabLds &L, const double *R, int ldr, int b, double *X,
+                                           int ldx, int J, const int *flag) {
+  const int f0 = flag[0];
+  const int t = threadIdx.x, cc = t & 15, g = t >> 4;
+  const int col = kSW * J + cc;
+  const int top = min(b, kSW * J + kSW);  // rows at or above the slab's last column
+  const int nb4 = (top + 3) / 4;
+  slab_load<false>(L, R, ldr, b, 0, 4 * nb4);  // through the last (padded) 4 x 4 block
   __syncthreads();
-  tile_load(T, c, s, Uinv, b, b);  // zeros below the diagonal, identity pad
+  if (f0) return;
+  if (t < nb4) {  // inverses of the 4 x 4 diagonal blocks
+    double a[kTE][kTE];
+#pragma unroll
+    for (int r = 0; r < kTE; ++r)
+#pragma unroll
+      for (int q = 0; q < kTE; ++q) a[r][q] = (q >= r) ? L.M[(4 * t + r) * kLdS + 4 * t + q] : 0.0;
+    inv4_upper(a);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) L.dg[t][4 * r + q] = a[r][q];
+  }
+  double B[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) B[k] = (g + 16 * k == col) ? 1.0 : 0.0;
   __syncthreads();
-  blk_inv_upper(T, c, s, b);
-  tile_store(T, c, s, Uinv, b, b, 1);
+  // Back substitution by 4-row blocks, bottom up, one barrier per block: the
+  // owners of the block's rows publish them, every thread then forms the
+  // block's solution for its own column (y = D^-1 x) and updates its rows
+  // above the block.  The 32 possible steps are unrolled so that every row
+  // index is static; steps beyond the slab are skipped (uniformly), and the
+  // R entries a step needs are read from LDS before the preceding barrier.
+  double mc[8][4], mn[8][4];
+#pragma unroll
+  for (int i4 = kNTl - 1; i4 >= 0; --i4) {
+    if (i4 < nb4) {
+      const int K = i4 >> 2, sub = i4 & 3, par = i4 & 1;
+      if (i4 == nb4 - 1) slab_fetch_above(L, g, i4, mc);
+      const bool own = (g >> 2) == sub;
+      if (own) L.xb[par][g & 3][cc] = B[K];
+      if (i4 > 0) slab_fetch_above(L, g, i4 - 1, mn);
+      __syncthreads();
+      double xv[4], y[4];
+#pragma unroll
+      for (int l = 0; l < 4; ++l) xv[l] = L.xb[par][l][cc];
+      const double *P = L.dg[i4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double acc = 0.0;
+#pragma unroll
+        for (int l = q; l < 4; ++l) acc += P[4 * q + l] * xv[l];
+        y[q] = acc;
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) B[k] -= mc[k][q] * y[q];
+      double u = B[K];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) u -= mc[K][q] * y[q];
+      const int gl = g & 3;
+      const double yo = gl == 0 ? y[0] : gl == 1 ? y[1] : gl == 2 ? y[2] : y[3];
+      B[K] = own ? yo : ((g >> 2) < sub ? u : B[K]);
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) mc[k][q] = mn[k][q];
+    }
+  }
+  if (col < b) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int r = g + 16 * k;
+      if (r < b) X[r + (int64_t)col * ldx] = B[k];
+    }
+  }
+}
+
+// T L^T = C with C = -U S (U upper, S = diag(sgn)), L unit lower (strict
+// part in V's top block): rows 16I .. 16I+15 of T in workgroup I, solved by
+// 4-column blocks left to right.  T is upper triangular; tau = diag(T).
+__device__ __forceinline__ void slab_tsolve(SlabLds &L, const double *U, const double *Vt,
+                                            int64_t ldv, const double *sgn, int b, double *Tout,
+                                            int ldt, double *tau, int I, const int *flag) {
+  const int f0 = flag[0];
+  const int t = threadIdx.x, rr = t & 15, g = t >> 4;
+  const int row = kSW * I + rr;
+  const int nb4 = (b + 3) / 4;
+  // L(j, l) for l < j, stored as M[j * kLdS + l]; only columns l >= 16 I
+  // (and rows below them) take part in this slab's solve
+  double Cv[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int j = g + 16 * k;
+    const bool in = row < b && j < b && j >= row;
+    const double u = U[in ? row + (int64_t)j * b : 0], sj = sgn[in ? j : 0];
+    Cv[k] = in ? -u * sj : 0.0;
+  }
+  slab_load<true>(L, Vt, ldv, b, kSW * I, 4 * nb4);
+  __syncthreads();
+  if (f0) return;
+  // forward by 4-column blocks, one barrier per block, unrolled like the
+  // back substitution of slab_trinv (steps outside the slab skipped
+  // uniformly, the L entries below the block read before the barrier)
+  const int j0 = (kSW * I) / 4;
+  double mc[8][4], mn[8][4];
+#pragma unroll
+  for (int j4 = 0; j4 < kNTl; ++j4) {
+    if (j4 >= j0 && j4 < nb4) {
+      const int K = j4 >> 2, sub = j4 & 3, par = j4 & 1;
+      if (j4 == j0) slab_fetch_below(L, g, j4, mc);
+      const bool own = (g >> 2) == sub;
+      if (own) L.xb[par][g & 3][rr] = Cv[K];
+      if (j4 + 1 < kNTl) slab_fetch_below(L, g, j4 + 1, mn);
+      __syncthreads();
+      // the block's 4 columns of this row: forward substitution with the unit
+      // lower diagonal block of L (every thread, for its own row)
+      double y[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double v = L.xb[par][q][rr];
+#pragma unroll
+        for (int l = 0; l < q; ++l) v -= y[l] * L.M[(4 * j4 + q) * kLdS + 4 * j4 + l];
+        y[q] = v;
+      }
+#pragma unroll
+      for (int k = K + 1; k < 8; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Cv[k] -= y[q] * mc[k][q];
+      double u = Cv[K];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) u -= y[q] * mc[K][q];
+      const int gl = g & 3;
+      const double yo = gl == 0 ? y[0] : gl == 1 ? y[1] : gl == 2 ? y[2] : y[3];
+      Cv[K] = own ? yo : ((g >> 2) > sub ? u : Cv[K]);
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) mc[k][q] = mn[k][q];
+    }
+  }
+  if (row < b) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int j = g + 16 * k;
+      if (j < b) {
+        const double v = (j >= row) ? Cv[k] : 0.0;
+        Tout[row + (int64_t)j * ldt] = v;
+        if (j == row) tau[row] = v;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kST) void k_trinv(const double *R, int ldr, int b, double *X, int ldx,
+                                               const int *flag) {
+  __shared__ SlabLds L;
+  slab_trinv(L, R, ldr, b, X, ldx, blockIdx.x, flag);
+}
+
+// workgroups 0 .. ns-1: rows of T; ns .. 2ns-1: columns of U^-1
+__global__ __launch_bounds__(kST) void k_recon_solve(const double *U, const double *V, int64_t ldv,
+                                                     const double *sgn, int b, double *Tout,
+                                                     int ldt, double *tau, double *Uinv,
+                                                     const int *flag) {
+  __shared__ SlabLds L;
+  const int ns = (b + kSW - 1) / kSW;
+  if ((int)blockIdx.x < ns)
+    slab_tsolve(L, U, V, ldv, sgn, b, Tout, ldt, tau, blockIdx.x, flag);
+  else
+    slab_trinv(L, U, b, b, Uinv, b, blockIdx.x - ns, flag);
 }
 
 // ---------------------------------------------------------------------------
@@ -602,16 +729,22 @@ int launch_lower_nonzero(const double *P, int64_t ldp, int rowmajor, int m, int 
 
 int launch_chol_inv(const double *G, int ldg, int b, double rel, double *R, double *Rinv, int *flag,
                     int check_structure, hipStream_t s) {
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(kRT), 0, s, G, ldg, b, rel, R, Rinv, flag,
-                     check_structure);
+  hipLaunchKernelGGL(k_chol, dim3(1), dim3(kRT), 0, s, G, ldg, b, rel, R, flag, check_structure);
+  BR_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_trinv, dim3((b + kSW - 1) / kSW), dim3(kST), 0, s, R, b, b, Rinv, b,
+                     (const int *)flag);
   BR_HIP_CHECK(hipGetLastError());
   return 0;
 }
 
 int launch_recon(const double *Qtop, int ldq, int b, double *V, int64_t ldv, double *T, int ldt,
-                 double *tau, double *Uinv, double *sgn, const int *flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_recon, dim3(1), dim3(kRT), 0, s, Qtop, ldq, b, V, ldv, T, ldt, tau, Uinv,
-                     sgn, flag);
+                 double *tau, double *Uinv, double *sgn, double *Uscr, const int *flag,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_lu, dim3(1), dim3(kRT), 0, s, Qtop, ldq, b, V, ldv, Uscr, sgn, flag);
+  BR_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_recon_solve, dim3(2 * ((b + kSW - 1) / kSW)), dim3(kST), 0, s,
+                     (const double *)Uscr, (const double *)V, ldv, (const double *)sgn, b, T, ldt,
+                     tau, Uinv, flag);
   BR_HIP_CHECK(hipGetLastError());
   return 0;
 }
