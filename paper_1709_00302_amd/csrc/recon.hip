@@ -39,6 +39,7 @@ namespace br {
 constexpr int kRT = 1024;          // threads of the register-tiled kernels
 constexpr int kTE = 4;             // tile edge
 constexpr int kNTl = kNbMax / kTE;  // tiles per edge (32)
+constexpr int kNB4 = kNbMax / kTE;  // 4-wide blocks per edge (32)
 
 struct Tile {
   double a[kTE][kTE];
@@ -425,10 +426,21 @@ __global__ __launch_bounds__(kRT) void k_lu(const double *Qtop, int ldq, int b, 
 // ---------------------------------------------------------------------------
 constexpr int kST = 256;           // threads of a slab workgroup
 constexpr int kSW = 16;            // slab width
-constexpr int kLdS = kNbMax + 1;   // LDS row stride of the b x b operand
+// The triangular operand is kept packed by columns (upper: column j holds
+// rows 0..j; strictly lower: rows j+1..127), about half the LDS of the full
+// square: at 70 KB a slab workgroup fits on a CU beside one workgroup of the
+// large GEMM tiles, so these kernels need not wait for a whole CU to drain
+// when they overlap the trailing update.  Reads of the other triangle (made
+// for rows whose result is then discarded) stay inside the padded array.
+constexpr int kPkPad = 16;
+constexpr int kPk = kPkPad + kNbMax * (kNbMax + 1) / 2 + 32;
+__device__ __forceinline__ int pk_up(int i, int j) { return kPkPad + j * (j + 1) / 2 + i; }
+__device__ __forceinline__ int pk_lo(int i, int j) {
+  return kPkPad + j * (2 * kNbMax - j - 1) / 2 + (i - j - 1);
+}
 
 struct SlabLds {
-  double M[kNbMax * kLdS];         // the triangular operand, M[i * kLdS + j] = op(i, j)
+  double M[kPk];                   // the triangular operand, packed
   double dg[kNbMax / 4][16];       // inverses of the 4 x 4 diagonal blocks
   double xb[2][4][kSW];            // the current 4-row (or 4-column) block, by parity
 };
@@ -459,7 +471,9 @@ __device__ __forceinline__ void slab_load(SlabLds &L, const double *G, int64_t l
       const int e = (int)threadIdx.x + kST * min(u0 + u, nper - 1);
       const int i = e & (kNbMax - 1), j = c0 + (e >> 7);
       const bool in = i < b && j < b && (!STRICT_LOWER || i > j);
-      L.M[i * kLdS + j] = in ? v[u] : ((!STRICT_LOWER && i == j) ? 1.0 : 0.0);
+      if (STRICT_LOWER ? (i > j) : (i <= j))
+        L.M[STRICT_LOWER ? pk_lo(i, j) : pk_up(i, j)] =
+            in ? v[u] : ((!STRICT_LOWER && i == j) ? 1.0 : 0.0);
     }
   }
 }
@@ -473,7 +487,7 @@ __device__ __forceinline__ void slab_fetch_above(const SlabLds &L, int g, int i4
   for (int k = 0; k < 8; ++k)
     if (k <= (i4 >> 2))
 #pragma unroll
-      for (int q = 0; q < 4; ++q) m[k][q] = L.M[(g + 16 * k) * kLdS + 4 * i4 + q];
+      for (int q = 0; q < 4; ++q) m[k][q] = L.M[pk_up(g + 16 * k, 4 * i4 + q)];
 }
 
 // M(r, 4 j4 + q), q < 4, for the rows r = g + 16 k with k >= j4 / 4.
@@ -483,7 +497,7 @@ __device__ __forceinline__ void slab_fetch_below(const SlabLds &L, int g, int j4
   for (int k = 0; k < 8; ++k)
     if (k >= (j4 >> 2))
 #pragma unroll
-      for (int q = 0; q < 4; ++q) m[k][q] = L.M[(g + 16 * k) * kLdS + 4 * j4 + q];
+      for (int q = 0; q < 4; ++q) m[k][q] = L.M[pk_lo(g + 16 * k, 4 * j4 + q)];
 }
 
 // X = R^-1 for the upper triangular R (columns 16J .. 16J+15 in workgroup J).
@@ -502,7 +516,7 @@ __device__ __forceinline__ void slab_trinv(SlabLds &L, const double *R, int ldr,
 #pragma unroll
     for (int r = 0; r < kTE; ++r)
 #pragma unroll
-      for (int q = 0; q < kTE; ++q) a[r][q] = (q >= r) ? L.M[(4 * t + r) * kLdS + 4 * t + q] : 0.0;
+      for (int q = 0; q < kTE; ++q) a[r][q] = (q >= r) ? L.M[pk_up(4 * t + r, 4 * t + q)] : 0.0;
     inv4_upper(a);
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -521,7 +535,7 @@ __device__ __forceinline__ void slab_trinv(SlabLds &L, const double *R, int ldr,
   // R entries a step needs are read from LDS before the preceding barrier.
   double mc[8][4], mn[8][4];
 #pragma unroll
-  for (int i4 = kNTl - 1; i4 >= 0; --i4) {
+  for (int i4 = kNB4 - 1; i4 >= 0; --i4) {
     if (i4 < nb4) {
       const int K = i4 >> 2, sub = i4 & 3, par = i4 & 1;
       if (i4 == nb4 - 1) slab_fetch_above(L, g, i4, mc);
@@ -575,7 +589,7 @@ __device__ __forceinline__ void slab_tsolve(SlabLds &L, const double *U, const d
   const int t = threadIdx.x, rr = t & 15, g = t >> 4;
   const int row = kSW * I + rr;
   const int nb4 = (b + 3) / 4;
-  // L(j, l) for l < j, stored as M[j * kLdS + l]; only columns l >= 16 I
+  // L(j, l) for l < j, packed by columns; only columns l >= 16 I
   // (and rows below them) take part in this slab's solve
   double Cv[8];
 #pragma unroll
@@ -594,13 +608,13 @@ __device__ __forceinline__ void slab_tsolve(SlabLds &L, const double *U, const d
   const int j0 = (kSW * I) / 4;
   double mc[8][4], mn[8][4];
 #pragma unroll
-  for (int j4 = 0; j4 < kNTl; ++j4) {
+  for (int j4 = 0; j4 < kNB4; ++j4) {
     if (j4 >= j0 && j4 < nb4) {
       const int K = j4 >> 2, sub = j4 & 3, par = j4 & 1;
       if (j4 == j0) slab_fetch_below(L, g, j4, mc);
       const bool own = (g >> 2) == sub;
       if (own) L.xb[par][g & 3][rr] = Cv[K];
-      if (j4 + 1 < kNTl) slab_fetch_below(L, g, j4 + 1, mn);
+      if (j4 + 1 < kNB4) slab_fetch_below(L, g, j4 + 1, mn);
       __syncthreads();
       // the block's 4 columns of this row: forward substitution with the unit
       // lower diagonal block of L (every thread, for its own row)
@@ -609,7 +623,7 @@ __device__ __forceinline__ void slab_tsolve(SlabLds &L, const double *U, const d
       for (int q = 0; q < 4; ++q) {
         double v = L.xb[par][q][rr];
 #pragma unroll
-        for (int l = 0; l < q; ++l) v -= y[l] * L.M[(4 * j4 + q) * kLdS + 4 * j4 + l];
+        for (int l = 0; l < q; ++l) v -= y[l] * L.M[pk_lo(4 * j4 + q, 4 * j4 + l)];
         y[q] = v;
       }
 #pragma unroll
