@@ -202,14 +202,29 @@ static int gemm(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int 
   d.gate = gate; d.gate_val = gate_val;
   const int bm = (M <= 64 && N <= 64) ? 64 : 128;
   const int tiles = ((M + bm - 1) / bm) * ((N + bm - 1) / bm);
-  const int target = 2 * cx.st->num_cu;
+  // workgroups resident at once: two per CU for the 128 x 128 tiles (VGPRs
+  // and LDS), four for the 64 x 64 ones
+  const int slots = (bm == 128 ? 2 : 4) * cx.st->num_cu;
   int ks = 1;
-  if (tiles < target && K > 512) {
-    ks = (target + tiles - 1) / tiles;
+  if (tiles < slots && K > 512) {
+    // split k so that the work runs in as few full rounds of resident
+    // workgroups as possible: the time goes as rounds x (k chunk), plus the
+    // reduction of the partial sums (memory bound, about one k unit per
+    // 2.5e6 elements of each partial)
     const int maxks = K / 256;
-    if (ks > maxks) ks = maxks;
-    if (ks < 1) ks = 1;
-    while (ks > 1 && (size_t)ks * M * N > cx.part_cap) --ks;
+    double best = 0.0;
+    for (int c = 1; c <= maxks; ++c) {
+      if ((size_t)c * M * N > cx.part_cap) break;
+      const int kc = (int)round_up((K + c - 1) / c, 128);
+      const int kk = (K + kc - 1) / kc;
+      const int rounds = (tiles * kk + slots - 1) / slots;
+      const double cost =
+          (double)rounds * kc + (kk > 1 ? (kk + 1) * ((double)M * N / 2.5e6) : 0.0);
+      if (c == 1 || cost < best - 1e-9) {
+        best = cost;
+        ks = kk;
+      }
+    }
   }
   const double flops = 2.0 * M * N * (double)K;
   if (ks == 1) {
