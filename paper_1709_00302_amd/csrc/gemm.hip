@@ -129,6 +129,64 @@ __device__ __forceinline__ void fetch_b(const GemmDesc &d, int j0, int k0, int k
   }
 }
 
+// Interior slices (the whole tile side in range, a full k slice, no diagonal
+// crossing for the symmetric operand) take a fast path: one uniform base per
+// slice plus a per-thread 32-bit element offset, without bounds tests, so the
+// loads go out as a short run of global loads with a scalar base.
+typedef __attribute__((address_space(1))) double gdbl;
+typedef __attribute__((address_space(1))) char gchr;
+__device__ __forceinline__ double gload(const double *p, uint32_t i) {
+  return *(const gdbl *)((const gchr *)p + (i << 3));
+}
+
+// A_SYM slice wholly below (mapping 0) or wholly above (mapping 1) the
+// diagonal; the plain operands are always pure
+template <int BM, int OPA>
+__device__ __forceinline__ bool a_pure(int i0, int k0) {
+  if (OPA != A_SYM) return true;
+  return (k0 + kBK - 1 <= i0) || (k0 >= i0 + BM - 1);
+}
+
+template <int BM, int OPA>
+__device__ __forceinline__ void fetch_a_fast(const GemmDesc &d, int i0, int k0, int mapping,
+                                             double *ra) {
+  constexpr int E = BM * kBK / kThreads;
+  const int tid = threadIdx.x;
+  // element (i, k) of op(A): stored at (i, k) for A_N and the lower part of
+  // A_SYM, at (k, i) for A_T and the upper part
+  const bool stored_ik = (OPA == A_N) || (OPA == A_SYM && mapping == 0);
+  const double *base = stored_ik ? d.A + i0 + (int64_t)k0 * d.lda : d.A + k0 + (int64_t)i0 * d.lda;
+  const uint32_t ld = (uint32_t)d.lda;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    int ii, kk;
+    map_elem<BM>(mapping, tid + kThreads * e, ii, kk);
+    const uint32_t off = stored_ik ? (uint32_t)ii + (uint32_t)kk * ld : (uint32_t)kk + (uint32_t)ii * ld;
+    ra[e] = gload(base, off);
+  }
+}
+
+template <int BN, int OPB>
+__device__ __forceinline__ void fetch_b_fast(const GemmDesc &d, int j0, int k0, double *rb) {
+  constexpr int E = BN * kBK / kThreads;
+  const int tid = threadIdx.x;
+  const int mapping = b_mapping<BN, OPB>();
+  int kb = k0;
+  if (OPB == B_TROT) {  // rot and K multiples of kBK: no wrap inside the slice
+    kb = k0 + d.rot;
+    if (kb >= d.K) kb -= d.K;
+  }
+  const double *base = (OPB == B_N) ? d.B + k0 + (int64_t)j0 * d.ldb : d.B + j0 + (int64_t)kb * d.ldb;
+  const uint32_t ld = (uint32_t)d.ldb;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    int jj, kk;
+    map_elem<BN>(mapping, tid + kThreads * e, jj, kk);
+    const uint32_t off = (OPB == B_N) ? (uint32_t)kk + (uint32_t)jj * ld : (uint32_t)jj + (uint32_t)kk * ld;
+    rb[e] = gload(base, off);
+  }
+}
+
 // registers -> LDS, converting to the stage type (hi/lo split for P_SPLIT)
 template <int BMN, int PREC, int LD>
 __device__ __forceinline__ void stash(typename Stage<PREC>::T *lds, int part_stride, int mapping,
@@ -210,10 +268,23 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm(GemmDesc d) {
   if (EPI == E_SYR2K) dd.N = d.c1;  // B operand rows are indexed by C's column
 
   const int nst = (kend - kbeg + kBK - 1) / kBK;
+  // fast loads: whole tile sides in range and 32-bit offsets within a slice
+  const int64_t ldmax = d.lda > d.ldb ? d.lda : d.ldb;
+  const bool rot_ok = (OPB != B_TROT) || ((d.rot | d.K) & (kBK - 1)) == 0;
+  const bool fast_tile = (i0 + BM <= dd.M) && (j0 + BN <= dd.N) && rot_ok &&
+                         ldmax * (BM > BN ? BM : BN) < ((int64_t)1 << 28);
+  auto fetch = [&](int k0, int mapping) {
+    if (fast_tile && k0 + kBK <= kend && a_pure<BM, OPA>(i0, k0)) {
+      fetch_a_fast<BM, OPA>(dd, i0, k0, mapping, ra);
+      fetch_b_fast<BN, OPB>(dd, j0, k0, rb);
+    } else {
+      fetch_a<BM, OPA>(dd, i0, k0, kend, mapping, ra);
+      fetch_b<BN, OPB>(dd, j0, k0, kend, rb);
+    }
+  };
   if (nst > 0) {
     int mapA = a_mapping<BM, OPA>(i0, kbeg);
-    fetch_a<BM, OPA>(dd, i0, kbeg, kend, mapA, ra);
-    fetch_b<BN, OPB>(dd, j0, kbeg, kend, rb);
+    fetch(kbeg, mapA);
     stash<BM, PREC, LDA_S>(As, SA, mapA, ra);
     stash<BN, PREC, LDB_S>(Bs, SB, b_mapping<BN, OPB>(), rb);
     __syncthreads();
@@ -224,8 +295,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm(GemmDesc d) {
       if (more) {
         const int k0 = kbeg + (s + 1) * kBK;
         mapN = a_mapping<BM, OPA>(i0, k0);
-        fetch_a<BM, OPA>(dd, i0, k0, kend, mapN, ra);
-        fetch_b<BN, OPB>(dd, j0, k0, kend, rb);
+        fetch(k0, mapN);
       }
       const T *as = As + buf * NP * SA;
       const T *bs = Bs + buf * NP * SB;
@@ -296,41 +366,53 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm(GemmDesc d) {
         for (int e = 0; e < 4; ++e) acc64[fm][fn][e] = (double)acc32[fm][fn][e];
   }
 
-  // epilogue.  C is read in groups of 16 values (one fm row of blocks) that
-  // are all loaded before any is stored, so the loads overlap instead of
-  // waiting behind the stores they might alias.
+  // epilogue.  C is read in groups of 16 values (one fm row of blocks), two
+  // groups in flight: the loads of group fm + 1 go out before group fm is
+  // stored (the registers of the operand staging are free by now), so the
+  // read latency is paid about once per tile instead of once per group.
   const bool readC = (EPI == E_SYR2K) || (EPI == E_AXPBY && d.beta != 0.0);
+  // the MFMA computed the transposed block (B^T A^T): its row index is C's
+  // column, its column index (lane % 16) is C's row, so 16 adjacent lanes
+  // touch 16 adjacent rows of one column (128 contiguous bytes)
+  auto row_of = [&](int fm) { return i0 + wm * (BM / 2) + fm * 16 + mfma_col(lane); };
+  auto col_of = [&](int fn, int e) { return j0 + wn * (BN / 2) + fn * 16 + mfma_row<PREC>(lane, e); };
+  auto inside = [&](int row, int col) {
+    bool in = (row < d.M && col < Nlim);
+    if (EPI == E_SYR2K) in = in && (row >= col);
+    return in;
+  };
+  double cv[2][FN][4];
+  auto load_c = [&](int fm, double (&c)[FN][4]) {
+    const int row = row_of(fm);
+#pragma unroll
+    for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int col = col_of(fn, e);
+        const bool in = inside(row, col);
+        const double x = d.C[in ? row + (int64_t)col * d.ldc : 0];  // clamped, no branch
+        c[fn][e] = in ? x : 0.0;
+      }
+  };
+  if (readC) load_c(0, cv[0]);
 #pragma unroll
   for (int fm = 0; fm < FM; ++fm) {
-    // the MFMA computed the transposed block (B^T A^T): its row index is
-    // C's column, its column index (lane % 16) is C's row, so 16 adjacent
-    // lanes touch 16 adjacent rows of one column (128 contiguous bytes)
-    const int row = i0 + wm * (BM / 2) + fm * 16 + mfma_col(lane);
-    double cv[FN][4];
-    bool ok[FN][4];
+    if (readC && fm + 1 < FM) load_c(fm + 1, cv[(fm + 1) & 1]);
+    const int row = row_of(fm);
 #pragma unroll
     for (int fn = 0; fn < FN; ++fn)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int col = j0 + wn * (BN / 2) + fn * 16 + mfma_row<PREC>(lane, e);
-        bool in = (row < d.M && col < Nlim);
-        if (EPI == E_SYR2K) in = in && (row >= col);
-        ok[fn][e] = in;
-        cv[fn][e] = (readC && in) ? d.C[row + (int64_t)col * d.ldc] : 0.0;
-      }
-#pragma unroll
-    for (int fn = 0; fn < FN; ++fn)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (!ok[fn][e]) continue;
-        const int col = j0 + wn * (BN / 2) + fn * 16 + mfma_row<PREC>(lane, e);
+        const int col = col_of(fn, e);
+        if (!inside(row, col)) continue;
         const double v = acc64[fm][fn][e];
+        const double c = cv[fm & 1][fn][e];
         if (EPI == E_AXPBY) {
-          d.C[row + (int64_t)col * d.ldc] = readC ? d.alpha * v + d.beta * cv[fn][e] : d.alpha * v;
+          d.C[row + (int64_t)col * d.ldc] = readC ? d.alpha * v + d.beta * c : d.alpha * v;
         } else if (EPI == E_PART) {
           d.part[(int64_t)blockIdx.z * d.M * d.N + row + (int64_t)col * d.M] = v;
         } else {
-          d.C[row + (int64_t)col * d.ldc] = cv[fn][e] - v;
+          d.C[row + (int64_t)col * d.ldc] = c - v;
         }
       }
   }
