@@ -367,13 +367,26 @@ def main():
                 out["tau"] = br.sy2sb(A, w, b, prec=prec)
         return run
 
-    run64 = runner("fp64")
+    run_eager = runner("fp64")
     log(f"bench: warmup {args.warmup}")
-    for _ in range(args.warmup):
+    for _ in range(max(1, args.warmup)):
         restore()
-        run64()
+        run_eager()
     torch.cuda.synchronize()
-    log(f"bench: timing {args.steps} steps")
+    # the timed steps replay the whole reduction captured in a HIP graph (the
+    # eager call above reserved the workspace); the same call without the
+    # graph is timed too and reported as the fp64_eager form
+    restore()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(stream)
+    with torch.cuda.stream(cs):
+        with torch.cuda.graph(graph, stream=cs):
+            run_eager()
+    torch.cuda.synchronize()
+    run64 = graph.replay
+    log(f"bench: timing {args.steps} steps (graph replay)")
     t_wall = time.perf_counter()
     times = time_steps(run64, restore, args.steps, stream)
     t_wall = time.perf_counter() - t_wall
@@ -400,7 +413,7 @@ def main():
     restore()
     torch.cuda.synchronize()
     br.bandred_profile_enable(True)
-    run64()
+    run_eager()  # per-launch events are recorded by eager calls only
     torch.cuda.synchronize()
     prof = br.bandred_profile_read()
     # the same step without look-ahead: every kernel alone on the GPU
@@ -436,6 +449,10 @@ def main():
                         for k, v in prof_serial.items() if v["launches"]}
 
     forms = {}
+    log("bench: eager calls (no graph)")
+    te = time_steps(run_eager, restore, max(2, args.steps // 2), stream)
+    forms["fp64_eager"] = {"gflops": flops / (statistics.median(te) / 1e3) / 1e9,
+                           "ms_per_step": statistics.median(te)}
     if not args.no_forms:
         for prec in ("fp32", "split32"):
             log(f"bench: form {prec}")
@@ -476,6 +493,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "w": w, "b": b,
                    **({"m": p["m"]} if is_ge else {}), "prec": "fp64", "lookahead": True,
+                   "launch": "HIP graph replay of the whole reduction",
                    "input": p["kind"] + (f", {p.get('spectrum')} spectrum" if "spectrum" in p else "")
                    + f", seed {p['seed']}"},
         "pct_fp64_peak": 100.0 * gflops / 1e3 / PEAK_TFLOPS["fp64"],

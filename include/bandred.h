@@ -103,14 +103,19 @@ BANDRED_API int bandred_ge2gb(int64_t m, int64_t n, int64_t w, int64_t b, double
 
 /* As bandred_sy2sb with a precision form, options and a stream
  * (hipStream_t, NULL = null stream).  Asynchronous: returns once the work is
- * enqueued (argument errors are reported synchronously).
+ * enqueued (argument errors are reported synchronously).  The call may be
+ * recorded into a HIP graph (stream capture) once an eager call of the same
+ * or a larger size has reserved the workspace; under capture it allocates
+ * nothing and returns BANDRED_ERR_UNSUPPORTED otherwise (or while profiling
+ * is enabled).  Replays share the device's workspace with every other call:
+ * the caller keeps them from overlapping.
  * Extra arguments: prec (arg 7), opts (arg 8, may be NULL), stream (arg 9). */
 BANDRED_API int bandred_sy2sb_ex(int64_t n, int64_t w, int64_t b, double *A, int64_t lda,
                      double *tau, int prec, const bandred_opts_t *opts,
                      void *stream);
 
 /* As bandred_ge2gb with prec (arg 9), opts (arg 10) and stream (arg 11);
- * asynchronous like bandred_sy2sb_ex. */
+ * asynchronous and capturable like bandred_sy2sb_ex. */
 BANDRED_API int bandred_ge2gb_ex(int64_t m, int64_t n, int64_t w, int64_t b, double *A,
                      int64_t lda, double *tauq, double *taup, int prec,
                      const bandred_opts_t *opts, void *stream);

@@ -160,6 +160,19 @@ static int ws_reserve(DevState &st, size_t bytes) {
   return 0;
 }
 
+// Stream capture (HIP graphs): a call recorded into a graph may not allocate
+// (the workspace must already be reserved by an earlier eager call at least
+// as large), skips the wait on and the record of the cross-call completion
+// event (the caller orders replays against other calls), and runs without
+// the profiling events.
+static int capture_check(hipStream_t s, size_t need, const DevState &st, bool *capturing) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  BR_HIP_CHECK(hipStreamIsCapturing(s, &cap));
+  *capturing = cap != hipStreamCaptureStatusNone;
+  if (*capturing && (g_prof || need > st.bytes)) return BANDRED_ERR_UNSUPPORTED;
+  return 0;
+}
+
 struct Arena {
   char *p;
   size_t off = 0;
@@ -422,6 +435,9 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
   need += 3 * round_up((size_t)(npan + 1) * 4, 256);     // counters, flags (2 per panel)
   need += 8192;
   std::lock_guard<std::mutex> lk(g_mu);
+  bool capturing = false;
+  rc = capture_check(s, need, *st, &capturing);
+  if (rc) return rc;
   rc = ws_reserve(*st, need);
   if (rc) return rc;
   Arena ar(st->base);
@@ -441,7 +457,7 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
   hipStream_t ps = lookahead ? st->aux : s;  // panel stream
   Ctx cxp{st, ps, partp, part_pan};
 
-  BR_HIP_CHECK(hipStreamWaitEvent(s, st->done, 0));
+  if (!capturing) BR_HIP_CHECK(hipStreamWaitEvent(s, st->done, 0));
   rc = launch_fill_u32(counters, npan + 1, 0u, s); if (rc) return rc;
   rc = launch_fill_u32((unsigned *)pflags, 2 * (npan + 1), 0u, s); if (rc) return rc;
   rc = launch_fill_u32((unsigned *)st->flags, 2, 0u, s); if (rc) return rc;
@@ -518,7 +534,7 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
       BR_HIP_CHECK(hipStreamWaitEvent(s, st->ev_b, 0));
     }
   }
-  BR_HIP_CHECK(hipEventRecord(st->done, s));
+  if (!capturing) BR_HIP_CHECK(hipEventRecord(st->done, s));
   return 0;
 }
 
@@ -552,6 +568,9 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
   need += 3 * round_up((size_t)(2 * npan + 2) * 4, 256);
   need += 8192;
   std::lock_guard<std::mutex> lk(g_mu);
+  bool capturing = false;
+  rc = capture_check(s, need, *st, &capturing);
+  if (rc) return rc;
   rc = ws_reserve(*st, need);
   if (rc) return rc;
   Arena ar(st->base);
@@ -570,7 +589,7 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
   hipStream_t ps = la ? st->aux : s;  // panel stream
   Ctx cxp{st, ps, partp, part_pan};  // panels: their own split-k buffer on either stream
 
-  BR_HIP_CHECK(hipStreamWaitEvent(s, st->done, 0));
+  if (!capturing) BR_HIP_CHECK(hipStreamWaitEvent(s, st->done, 0));
   rc = launch_fill_u32(counters, 2 * npan + 2, 0u, s); if (rc) return rc;
   rc = launch_fill_u32((unsigned *)pflags, 2 * (2 * npan + 2), 0u, s); if (rc) return rc;
   rc = launch_fill_u32((unsigned *)st->flags, 2, 0u, s); if (rc) return rc;
@@ -688,7 +707,7 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
       }
     }
   }
-  BR_HIP_CHECK(hipEventRecord(st->done, s));
+  if (!capturing) BR_HIP_CHECK(hipEventRecord(st->done, s));
   return 0;
 }
 

@@ -137,3 +137,34 @@ def test_known_spectrum_config(bandred, orc):
     assert err["orth"] <= 1e-14 * n
     assert err["eig_err"] <= 1e-14 * n
     assert err["band_trunc"] <= 1e-14 * n
+
+
+@pytest.mark.parametrize("n,w,b", [(700, 96, 64), (1000, 128, 128), (300, 16, 16)])
+def test_sy2sb_graph_replay_matches_eager(bandred, n, w, b):
+    print(f"case sy2sb graph n={n} w={w} b={b}", flush=True)
+    """The whole reduction captured in a HIP graph (after one eager call of
+    the same size) and replayed three times, with eager work in between: every
+    replay equals the eager result bit for bit (same kernels, same order)."""
+    A = inputs.sym_normal(n, 41)
+    A0, _ = to_device_colmajor(A, n)
+    Ad = A0.clone()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        tau_e = bandred.sy2sb(Ad, w, b, stream=s)
+    torch.cuda.synchronize()
+    ref, tref = Ad.clone(), tau_e.clone()
+    Ad.copy_(A0)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            tau_g = bandred.sy2sb(Ad, w, b, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        Ad.copy_(A0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()  # eager work between replays
+        assert torch.equal(Ad, ref), rep
+        assert torch.equal(tau_g, tref), rep
