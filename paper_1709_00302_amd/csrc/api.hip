@@ -241,6 +241,9 @@ static int gemm(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int 
   }
   const double flops = 2.0 * M * N * (double)K;
   if (ks == 1) {
+    // too few 128 x 128 tiles to occupy every CU and no k split: 64 x 64
+    // tiles give four times the workgroups
+    if (bm == 128 && tiles < cx.st->num_cu) d.tile64 = 1;
     d.kchunk = (int)round_up(K, kBK);
     ProfScope ps(cls, flops, s);
     return launch_gemm(opa, opb, E_AXPBY, prec, d, 1, s);
@@ -267,6 +270,11 @@ static int syr2k(Ctx &cx, int prec, int j, int pb, const double *WV, int64_t ldw
   d.C = A2; d.ldc = lda;
   d.rot = pb; d.c0 = c0; d.c1 = c1;
   d.kchunk = 2 * pb;
+  {  // lower tiles of 128 x 128 in the column range; 64 x 64 below one per CU
+    const int nI = (j - c0 + 127) / 128, nJ = (c1 - c0 + 127) / 128;
+    const int64_t lower = (int64_t)nJ * nI - (int64_t)nJ * (nJ - 1) / 2;
+    if (lower < cx.st->num_cu) d.tile64 = 1;
+  }
   // lower-trapezoid flops of the column range
   const double rows0 = (double)(j - c0), rows1 = (double)(j - c1);
   const double elems = 0.5 * (rows0 * (rows0 + 1) - rows1 * (rows1 + 1));

@@ -48,6 +48,7 @@ struct GemmDesc {
   int c0, c1;      // E_SYR2K: columns [c0, c1) of C, rows >= c0
   const int *gate; // when set, the kernel runs only if *gate == gate_val
   int gate_val;
+  int tile64;      // nonzero: 64 x 64 output tiles (4x the workgroups of 128 x 128)
 };
 
 struct PanelDesc {

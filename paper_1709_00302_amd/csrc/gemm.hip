@@ -484,8 +484,10 @@ static int dispatch_ops(int opa, int opb, int epi, const GemmDesc &d, int ksplit
 int launch_gemm(int opa, int opb, int epi, int prec, const GemmDesc &d, int ksplit,
                 hipStream_t s) {
   // 64 x 64 tiles for outputs up to 128 x 128 (the b x b products and Gram
-  // matrices), so that such products still spread over several workgroups
-  const bool small = (d.M <= 128 && (epi == E_SYR2K ? (d.c1 - d.c0) : d.N) <= 128);
+  // matrices), so that such products still spread over several workgroups,
+  // and when the caller asks for them (products with fewer 128 x 128 tiles
+  // than CUs and no k split)
+  const bool small = d.tile64 || (d.M <= 128 && (epi == E_SYR2K ? (d.c1 - d.c0) : d.N) <= 128);
   int rc;
   if (prec == P_F64) {
     rc = small ? dispatch_ops<64, 64, P_F64>(opa, opb, epi, d, ksplit, s)
