@@ -425,8 +425,18 @@ __global__ void k_reduce_partials(const double *part, int ksplit, int M, int N, 
   const int64_t total = (int64_t)M * N;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
+    // the partials are loaded eight at a time (independent loads, one memory
+    // latency per group instead of per partial) and summed in z order
     double s = 0.0;
-    for (int z = 0; z < ksplit; ++z) s += part[z * total + idx];
+    int z = 0;
+    for (; z + 8 <= ksplit; z += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(z + u) * total + idx];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; z < ksplit; ++z) s += part[z * total + idx];
     const int64_t i = idx % M, j = idx / M;
     double *c = C + i + j * ldc;
     *c = (beta == 0.0) ? alpha * s : alpha * s + beta * (*c);
