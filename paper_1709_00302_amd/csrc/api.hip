@@ -202,7 +202,8 @@ struct Ctx {
 static int gemm(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int K,
                 const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
                 int64_t ldc, double alpha, double beta, hipStream_t s,
-                const int *gate = nullptr, int gate_val = 0) {
+                const int *gate = nullptr, int gate_val = 0, double *C2 = nullptr,
+                int64_t ldc2 = 0, int c2_trans = 0) {
   if (M <= 0 || N <= 0) return 0;
   if (K <= 0) {
     if (beta == 1.0) return 0;
@@ -213,13 +214,14 @@ static int gemm(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int 
   d.A = A; d.lda = lda; d.B = B; d.ldb = ldb; d.C = C; d.ldc = ldc;
   d.alpha = alpha; d.beta = beta;
   d.gate = gate; d.gate_val = gate_val;
+  d.C2 = C2; d.ldc2 = ldc2; d.c2_trans = c2_trans;
   const int bm = (M <= 64 && N <= 64) ? 64 : 128;
   const int tiles = ((M + bm - 1) / bm) * ((N + bm - 1) / bm);
   // workgroups resident at once: two per CU for the 128 x 128 tiles (VGPRs
   // and LDS), four for the 64 x 64 ones
   const int slots = (bm == 128 ? 2 : 4) * cx.st->num_cu;
   int ks = 1;
-  if (tiles < slots && K > 512) {
+  if (tiles < slots && K > 512 && !C2) {  // (the second output needs a single pass)
     // split k so that the work runs in as few full rounds of resident
     // workgroups as possible: the time goes as rounds x (k chunk), plus the
     // reduction of the partial sums (memory bound, about one k unit per
@@ -392,13 +394,18 @@ static int panel_factor(Ctx &cx, bool rowmajor, double *P, int64_t ldp, int m, i
             s, flag, 0);
   if (rc) return rc;
   if (m > nb) {
+    // rows nb.. of the factored panel are those of V: the product stores them
+    // to the panel as well (in place, transposed for a row panel), so the
+    // finalisation below only writes the top nb x nb block
     rc = gemm(cx, C_PANEL, A_N, B_N, P_F64, m - nb, nb, nb, pw.Q1 + nb, m, pw.M, nb, V + nb, ldv,
-              1.0, 0.0, s, flag, 0);
+              1.0, 0.0, s, flag, 0, rowmajor ? P + (int64_t)nb * ldp : P + nb, ldp,
+              rowmajor ? 1 : 0);
     if (rc) return rc;
   }
   {
     ProfScope p2(C_PANEL_SMALL, flops, s);
-    rc = launch_panel_finalize(P, ldp, rowmajor ? 1 : 0, m, nb, V, ldv, pw.Rh0, pw.sgn, flag, s);
+    rc = launch_panel_finalize(P, ldp, rowmajor ? 1 : 0, std::min(m, nb), nb, V, ldv, pw.Rh0,
+                               pw.sgn, flag, s);
     if (rc) return rc;
   }
   // fallback for flagged (rank-deficient) panels

@@ -49,6 +49,9 @@ struct GemmDesc {
   const int *gate; // when set, the kernel runs only if *gate == gate_val
   int gate_val;
   int tile64;      // nonzero: 64 x 64 output tiles (4x the workgroups of 128 x 128)
+  double *C2;      // E_AXPBY: when set, every stored value also goes to C2 ...
+  int64_t ldc2;
+  int c2_trans;    // ... at (row, col) (ld ldc2), or transposed at (col, row)
 };
 
 struct PanelDesc {

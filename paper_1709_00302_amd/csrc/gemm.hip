@@ -408,7 +408,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm(GemmDesc d) {
         const double v = acc64[fm][fn][e];
         const double c = cv[fm & 1][fn][e];
         if (EPI == E_AXPBY) {
-          d.C[row + (int64_t)col * d.ldc] = readC ? d.alpha * v + d.beta * c : d.alpha * v;
+          const double o = readC ? d.alpha * v + d.beta * c : d.alpha * v;
+          d.C[row + (int64_t)col * d.ldc] = o;
+          if (d.C2) {
+            if (d.c2_trans) d.C2[col + (int64_t)row * d.ldc2] = o;
+            else d.C2[row + (int64_t)col * d.ldc2] = o;
+          }
         } else if (EPI == E_PART) {
           d.part[(int64_t)blockIdx.z * d.M * d.N + row + (int64_t)col * d.M] = v;
         } else {
