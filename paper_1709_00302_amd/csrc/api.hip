@@ -215,6 +215,7 @@ static int gemm(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int 
   d.alpha = alpha; d.beta = beta;
   d.gate = gate; d.gate_val = gate_val;
   d.C2 = C2; d.ldc2 = ldc2; d.c2_trans = c2_trans;
+  d.prio = (cls == C_PANEL || cls == C_GEMM_SMALL) ? 1 : 0;
   const int bm = (M <= 64 && N <= 64) ? 64 : 128;
   const int tiles = ((M + bm - 1) / bm) * ((N + bm - 1) / bm);
   // workgroups resident at once: two per CU for the 128 x 128 tiles (VGPRs
@@ -282,6 +283,68 @@ static int syr2k(Ctx &cx, int prec, int j, int pb, const double *WV, int64_t ldw
   const double elems = 0.5 * (rows0 * (rows0 + 1) - rows1 * (rows1 + 1));
   ProfScope ps(C_SYR2K, 2.0 * 2.0 * pb * elems, s);
   return launch_gemm(A_N, B_TROT, E_SYR2K, prec, d, 1, s);
+}
+
+// Trailing updates that run beside a panel factorisation are issued as a few
+// consecutive launches over column chunks instead of one.  The single-workgroup
+// b x b kernels of the panel need a whole CU, which a running update never
+// frees (a finished workgroup's slot is refilled at once); between two launches
+// on one stream the CUs drain, and a waiting panel kernel takes one.  At most
+// three chunks (two drains for the panel's three such kernels: fewer chunks
+// leave them waiting longer, more add launch tails that cost more than they
+// save), each at least two full rounds of resident 128 x 128 workgroups.
+// Every element is still computed by one tile in the same order.
+constexpr int kMaxChunks = 3;
+static int update_chunks(const DevState *st, int64_t tiles128) {
+  const int64_t per = 4 * (int64_t)st->num_cu;  // two rounds of two workgroups per CU
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxChunks, tiles128 / per));
+}
+
+// syr2k over columns [c0, c1) as update_chunks() launches of about equal
+// lower-trapezoid area, boundaries on 128-column tiles.
+static int syr2k_chunked(Ctx &cx, int prec, int j, int pb, const double *WV, int64_t ldwv,
+                         double *A2, int64_t lda, int c0, int c1, hipStream_t s) {
+  if (c1 <= c0) return 0;
+  const int64_t nI = (j - c0 + 127) / 128, nJ = (c1 - c0 + 127) / 128;
+  const int nck = update_chunks(cx.st, nJ * nI - nJ * (nJ - 1) / 2);
+  auto area = [&](double x) {  // lower-trapezoid elements of columns [c0, x)
+    const double r0 = j - c0, r1 = j - x;
+    return 0.5 * (r0 * (r0 + 1) - r1 * (r1 + 1));
+  };
+  const double tot = area(c1);
+  int lo = c0;
+  for (int k = 1; k <= nck; ++k) {
+    int hi = c1;
+    if (k < nck) {
+      // smallest tile boundary whose area reaches k / nck of the total
+      hi = lo;
+      while (hi < c1 && area(hi) < tot * k / nck) hi = std::min(c1, hi + 128);
+    }
+    int rc = syr2k(cx, prec, j, pb, WV, ldwv, A2, lda, lo, hi, s);
+    if (rc) return rc;
+    lo = hi;
+  }
+  return 0;
+}
+
+// C(M x N) = alpha op(A) op(B) + beta C with K <= 512 (no k split) as
+// update_chunks() launches over column chunks of 128-multiples.
+static int gemm_chunked(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int K,
+                        const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
+                        int64_t ldc, double alpha, double beta, hipStream_t s) {
+  const int64_t tiles = (int64_t)((M + 127) / 128) * ((N + 127) / 128);
+  const int nck = (K <= 512) ? update_chunks(cx.st, tiles) : 1;
+  const int nt = (N + 127) / 128;
+  for (int k = 0, n0 = 0; k < nck && n0 < N; ++k) {
+    const int n1 = (k == nck - 1) ? N : std::min(N, 128 * (int)((int64_t)nt * (k + 1) / nck));
+    if (n1 <= n0) continue;
+    const double *Bk = (opb == B_N) ? B + (int64_t)n0 * ldb : B + n0;
+    int rc = gemm(cx, cls, opa, opb, prec, M, n1 - n0, K, A, lda, Bk, ldb,
+                  C + (int64_t)n0 * ldc, ldc, alpha, beta, s);
+    if (rc) return rc;
+    n0 = n1;
+  }
+  return 0;
 }
 
 // Scratch of one panel factorisation.
@@ -542,7 +605,11 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
       rc = fork_next();
       if (rc) return rc;
     }
-    rc = syr2k(cxm, prec, j, pb, WV, j, A2, lda, a2L, j, s);
+    // the rest beside the next panel: in chunks (see update_chunks)
+    if (has_next && ps != s)
+      rc = syr2k_chunked(cxm, prec, j, pb, WV, j, A2, lda, a2L, j, s);
+    else
+      rc = syr2k(cxm, prec, j, pb, WV, j, A2, lda, a2L, j, s);
     if (rc) return rc;
     if (has_next && ps != s) {
       BR_HIP_CHECK(hipEventRecord(st->ev_b, ps));
@@ -665,8 +732,8 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
         rc = right_panel(it, cxp, ps);  // (3) overlaps the rest of (2)
         if (rc) return rc;
         BR_HIP_CHECK(hipEventRecord(st->ev_d, ps));
-        rc = gemm(cx, C_GEMM_UPD, A_N, B_N, prec, i - top, ne, pb, Vq + top, i, Zb, pb,
-                  E + top, lda, -1.0, 1.0, s);
+        rc = gemm_chunked(cx, C_GEMM_UPD, A_N, B_N, prec, i - top, ne, pb, Vq + top, i, Zb, pb,
+                          E + top, lda, -1.0, 1.0, s);
         if (rc) return rc;
         BR_HIP_CHECK(hipStreamWaitEvent(s, st->ev_d, 0));
       } else if (pr > 0) {
@@ -698,8 +765,8 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
           if (rc) return rc;
           BR_HIP_CHECK(hipEventRecord(st->ev_b, ps));
           if (jr > lcols) {
-            rc = gemm(cx, C_GEMM_UPD, A_N, B_T, prec, md, jr - lcols, pr, Xb, md, Up + lcols, jr,
-                      D + (int64_t)lcols * lda, lda, -1.0, 1.0, s);
+            rc = gemm_chunked(cx, C_GEMM_UPD, A_N, B_T, prec, md, jr - lcols, pr, Xb, md,
+                              Up + lcols, jr, D + (int64_t)lcols * lda, lda, -1.0, 1.0, s);
             if (rc) return rc;
           }
           BR_HIP_CHECK(hipStreamWaitEvent(s, st->ev_b, 0));

@@ -52,7 +52,15 @@ struct GemmDesc {
   double *C2;      // E_AXPBY: when set, every stored value also goes to C2 ...
   int64_t ldc2;
   int c2_trans;    // ... at (row, col) (ld ldc2), or transposed at (col, row)
+  int prio;        // nonzero: the waves run at raised issue priority (panel products)
 };
+
+// Wave issue priority of the panel kernels.  The panel of the next step runs
+// beside the trailing update (look-ahead) and is the longer of the two; at a
+// raised priority its waves are issued ahead of the update's waves on a
+// shared SIMD.  kPrioCrit is for the one wave on the Cholesky / LU pivot chain.
+constexpr int kPrioPanel = 2;
+constexpr int kPrioCrit = 3;
 
 struct PanelDesc {
   double *P;        // panel, element (r,k) at P[r*rs + k*cs]

@@ -230,6 +230,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm(GemmDesc d) {
   __shared__ T Bs[2 * NP * SB];
 
   if (d.gate && *d.gate != d.gate_val) return;
+  if (d.prio) __builtin_amdgcn_s_setprio(kPrioPanel);
   int i0, j0, kbeg, kend;
   if (EPI == E_SYR2K) {
     const int I = blockIdx.x, J = blockIdx.y;
@@ -427,6 +428,7 @@ __global__ void k_reduce_partials(const double *part, int ksplit, int M, int N, 
                                   double *C, int64_t ldc, double beta, const int *gate,
                                   int gate_val) {
   if (gate && *gate != gate_val) return;
+  __builtin_amdgcn_s_setprio(kPrioPanel);  // split-k sums: on the panel chain or alone
   const int64_t total = (int64_t)M * N;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {

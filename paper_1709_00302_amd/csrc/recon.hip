@@ -185,8 +185,8 @@ __device__ __forceinline__ void tile_store(const Tile &T, const TileCtx &c, Bcas
 // published that row, so that its own trailing update is not slowed down by
 // the other waves of its SIMD.
 __device__ __forceinline__ void prio_next(const TileCtx &c, int kb) {
-  if ((c.t >> 6) == ((kb + 1) >> 1)) __builtin_amdgcn_s_setprio(3);
-  else __builtin_amdgcn_s_setprio(0);
+  if ((c.t >> 6) == ((kb + 1) >> 1)) __builtin_amdgcn_s_setprio(kPrioCrit);
+  else __builtin_amdgcn_s_setprio(kPrioPanel);
 }
 
 // Blocked upper Cholesky in place: G = R^T R, R in the upper triangle.  The
@@ -246,7 +246,7 @@ __device__ __forceinline__ bool blk_chol(Tile &T, const TileCtx &c, Bcast &s, in
       }
     }
   }
-  __builtin_amdgcn_s_setprio(0);
+  __builtin_amdgcn_s_setprio(kPrioPanel);
   __syncthreads();
   return s.bad == 0;
 }
@@ -378,6 +378,7 @@ __device__ __forceinline__ void blk_lu_sign(Tile &T, const TileCtx &c, Bcast &s,
 __global__ __launch_bounds__(kRT) void k_chol(const double *G, int ldg, int b, double rel,
                                               double *R, int *flag, int check_structure) {
   __shared__ Bcast s;
+  __builtin_amdgcn_s_setprio(kPrioPanel);
   // the flags are read before, and tested after, the matrix loads so that the
   // two memory latencies overlap
   const int f0 = flag[0], f1 = flag[1];
@@ -407,6 +408,7 @@ __global__ __launch_bounds__(kRT) void k_chol(const double *G, int ldg, int b, d
 __global__ __launch_bounds__(kRT) void k_lu(const double *Qtop, int ldq, int b, double *V,
                                             int64_t ldv, double *U, double *sgn, const int *flag) {
   __shared__ Bcast s;
+  __builtin_amdgcn_s_setprio(kPrioPanel);
   const int f0 = flag[0];
   const TileCtx c = tile_ctx();
   Tile T;
@@ -658,6 +660,7 @@ __device__ __forceinline__ void slab_tsolve(SlabLds &L, const double *U, const d
 __global__ __launch_bounds__(kST) void k_trinv(const double *R, int ldr, int b, double *X, int ldx,
                                                const int *flag) {
   __shared__ SlabLds L;
+  __builtin_amdgcn_s_setprio(kPrioPanel);
   slab_trinv(L, R, ldr, b, X, ldx, blockIdx.x, flag);
 }
 
@@ -667,6 +670,7 @@ __global__ __launch_bounds__(kST) void k_recon_solve(const double *U, const doub
                                                      int ldt, double *tau, double *Uinv,
                                                      const int *flag) {
   __shared__ SlabLds L;
+  __builtin_amdgcn_s_setprio(kPrioPanel);
   const int ns = (b + kSW - 1) / kSW;
   if ((int)blockIdx.x < ns)
     slab_tsolve(L, U, V, ldv, sgn, b, Tout, ldt, tau, blockIdx.x, flag);
@@ -683,6 +687,7 @@ __global__ void k_panel_finalize(double *P, int64_t ldp, int rowmajor, int m, in
                                  const double *V, int64_t ldv, const double *Rh0,
                                  const double *sgn, const int *flag) {
   if (flag[0]) return;
+  __builtin_amdgcn_s_setprio(kPrioPanel);
   const int64_t total = (int64_t)m * b;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -707,6 +712,7 @@ __global__ void k_panel_finalize(double *P, int64_t ldp, int rowmajor, int m, in
 __global__ void k_lower_nonzero(const double *P, int64_t ldp, int rowmajor, int m, int b,
                                 int *count) {
   __shared__ int found;
+  __builtin_amdgcn_s_setprio(kPrioPanel);
   if (threadIdx.x == 0) found = 0;
   __syncthreads();
   const int64_t total = (int64_t)m * b;
