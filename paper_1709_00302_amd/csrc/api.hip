@@ -398,11 +398,13 @@ static int panel_columns(Ctx &cx, bool rowmajor, double *P, int64_t ldp, int m, 
 // in-place R / v storage, explicit V (m x nb, ld ldv), tau and T (nb x nb).
 //   method 1: per-column kernel + S = V^T V + T recurrence.
 //   method 0/2: CholeskyQR2 + Householder reconstruction; if the first
-//   Cholesky flags the panel as rank deficient, the per-column path runs
-//   instead (all kernels are gated on the device flag, no host round trip).
+//   Cholesky flags the panel (rank deficient, or a column that is zero below
+//   its diagonal by the panel's structure), the per-column path runs instead
+//   (all kernels are gated on the device flag, no host round trip).
 static int panel_factor(Ctx &cx, bool rowmajor, double *P, int64_t ldp, int m, int nb, double *V,
                         int64_t ldv, double *tau, double *T, int ldt, PanelWs &pw,
-                        unsigned *counter, int *flag, int method, int panel_rows, hipStream_t s) {
+                        unsigned *counter, int *flag, int *structure, int method, int panel_rows,
+                        hipStream_t s) {
   int rc;
   // a square panel's last column has no rows below the diagonal (tau = 0 by
   // the Householder convention): factor it column by column
@@ -417,7 +419,7 @@ static int panel_factor(Ctx &cx, bool rowmajor, double *P, int64_t ldp, int m, i
     return launch_larft(pw.S, nb, tau, nb, T, ldt, s);
   }
   const double flops = 2.0 * (double)m * nb * nb;
-  rc = launch_lower_nonzero(P, ldp, rowmajor ? 1 : 0, m, nb, flag + 1, s);
+  rc = launch_panel_structure(P, ldp, rowmajor ? 1 : 0, m, nb, structure, s);
   if (rc) return rc;
   // G = P^T P ; R1 = chol(G), R1^-1
   rc = gemm(cx, C_PANEL, rowmajor ? A_N : A_T, rowmajor ? B_T : B_N, P_F64, nb, nb, m, P, ldp, P,
@@ -425,7 +427,7 @@ static int panel_factor(Ctx &cx, bool rowmajor, double *P, int64_t ldp, int m, i
   if (rc) return rc;
   {
     ProfScope p2(C_PANEL_SMALL, 0.0, s);
-    rc = launch_chol_inv(pw.G, nb, nb, 1e-10, pw.R1, pw.R1i, flag, 1, s);
+    rc = launch_chol_inv(pw.G, nb, nb, 1e-10, pw.R1, pw.R1i, flag, structure, s);
     if (rc) return rc;
   }
   // Q1 = P R1^-1 ; G2 = Q1^T Q1 ; R2 = chol(G2), R2^-1
@@ -437,7 +439,7 @@ static int panel_factor(Ctx &cx, bool rowmajor, double *P, int64_t ldp, int m, i
   if (rc) return rc;
   {
     ProfScope p2(C_PANEL_SMALL, 0.0, s);
-    rc = launch_chol_inv(pw.G2, nb, nb, 1e-6, pw.R2, pw.R2i, flag, 0, s);
+    rc = launch_chol_inv(pw.G2, nb, nb, 1e-6, pw.R2, pw.R2i, flag, nullptr, s);
     if (rc) return rc;
   }
   // Qtop = Q1(0:nb, :) R2^-1 ; LU with signs, T, U^-1
@@ -471,7 +473,8 @@ static int panel_factor(Ctx &cx, bool rowmajor, double *P, int64_t ldp, int m, i
                                pw.sgn, flag, s);
     if (rc) return rc;
   }
-  // fallback for flagged (rank-deficient) panels
+  // fallback for flagged panels (rank deficient or with a structurally zero
+  // column): every kernel is gated on the flag
   rc = panel_columns(cx, rowmajor, P, ldp, m, nb, V, ldv, tau, pw, counter, panel_rows, flag, 1, s);
   if (rc) return rc;
   rc = gemm(cx, C_GEMM_SMALL, A_T, B_N, P_F64, nb, nb, m, V, ldv, V, ldv, pw.S, nb, 1.0, 0.0, s,
@@ -511,6 +514,7 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
   need += 4 * round_up((size_t)b * std::max(b, w) * 8, 256);  // T[2], M, Z
   need += PanelWs::bytes(jmax, b);
   need += 3 * round_up((size_t)(npan + 1) * 4, 256);     // counters, flags (2 per panel)
+  need += round_up((size_t)(npan + 1) * 2 * kNbMax * 4, 256);  // panel structure
   need += 8192;
   std::lock_guard<std::mutex> lk(g_mu);
   bool capturing = false;
@@ -530,6 +534,7 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
   pw.carve(ar, jmax, b);
   unsigned *counters = ar.take<unsigned>(npan + 1);
   int *pflags = ar.take<int>(2 * (npan + 1));
+  int *pstruct = ar.take<int>((size_t)(npan + 1) * 2 * kNbMax);
 
   Ctx cxm{st, s, partm, part_main};
   hipStream_t ps = lookahead ? st->aux : s;  // panel stream
@@ -538,6 +543,8 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
   if (!capturing) BR_HIP_CHECK(hipStreamWaitEvent(s, st->done, 0));
   rc = launch_fill_u32(counters, npan + 1, 0u, s); if (rc) return rc;
   rc = launch_fill_u32((unsigned *)pflags, 2 * (npan + 1), 0u, s); if (rc) return rc;
+  rc = launch_fill_u32((unsigned *)pstruct, (int64_t)(npan + 1) * 2 * kNbMax, 0u, s);
+  if (rc) return rc;
   rc = launch_fill_u32((unsigned *)st->flags, 2, 0u, s); if (rc) return rc;
   rc = launch_fill(tau, n - w, 0.0, s); if (rc) return rc;
 
@@ -546,7 +553,8 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
     const int c = it * b, pb = std::min(b, nref - c), r = c + w, j = n - r;
     double *V = WVbuf[it & 1] + (int64_t)pb * j;
     int e = panel_factor(cx, false, A + r + (int64_t)c * lda, lda, j, pb, V, j, tau + c,
-                         Tb[it & 1], pb, pw, counters + it, pflags + 2 * it, method, panel_rows, q);
+                         Tb[it & 1], pb, pw, counters + it, pflags + 2 * it,
+                         pstruct + (size_t)it * 2 * kNbMax, method, panel_rows, q);
     if (e) return e;
     return gemm(cx, C_GEMM_SMALL, A_N, B_N, P_F64, j, pb, pb, V, j, Tb[it & 1], pb, Wtb[it & 1], j,
                 1.0, 0.0, q);
@@ -648,6 +656,7 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
   need += 2 * round_up((size_t)b * b * 8, 256);       // Tq, Tp
   need += PanelWs::bytes(m, b);
   need += 3 * round_up((size_t)(2 * npan + 2) * 4, 256);
+  need += round_up((size_t)(2 * npan + 2) * 2 * kNbMax * 4, 256);  // panel structure
   need += 8192;
   std::lock_guard<std::mutex> lk(g_mu);
   bool capturing = false;
@@ -667,6 +676,7 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
   pw.carve(ar, m, b);
   unsigned *counters = ar.take<unsigned>(2 * npan + 2);
   int *pflags = ar.take<int>(2 * (2 * npan + 2));
+  int *pstruct = ar.take<int>((size_t)(2 * npan + 2) * 2 * kNbMax);
   Ctx cx{st, s, part, part_cap};
   hipStream_t ps = la ? st->aux : s;  // panel stream
   Ctx cxp{st, ps, partp, part_pan};  // panels: their own split-k buffer on either stream
@@ -674,6 +684,8 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
   if (!capturing) BR_HIP_CHECK(hipStreamWaitEvent(s, st->done, 0));
   rc = launch_fill_u32(counters, 2 * npan + 2, 0u, s); if (rc) return rc;
   rc = launch_fill_u32((unsigned *)pflags, 2 * (2 * npan + 2), 0u, s); if (rc) return rc;
+  rc = launch_fill_u32((unsigned *)pstruct, (int64_t)(2 * npan + 2) * 2 * kNbMax, 0u, s);
+  if (rc) return rc;
   rc = launch_fill_u32((unsigned *)st->flags, 2, 0u, s); if (rc) return rc;
   rc = launch_fill(tauq, n, 0.0, s); if (rc) return rc;
   rc = launch_fill(taup, n, 0.0, s); if (rc) return rc;
@@ -682,7 +694,8 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
   auto left_panel = [&](int it, Ctx &c_, hipStream_t q) -> int {
     const int c = it * b, pb = std::min(b, n - c), i = m - c;
     int r = panel_factor(c_, false, A + c + (int64_t)c * lda, lda, i, pb, Vq, i, tauq + c, Tq, pb,
-                         pw, counters + 2 * it, pflags + 4 * it, method, panel_rows, q);
+                         pw, counters + 2 * it, pflags + 4 * it,
+                         pstruct + (size_t)(2 * it) * 2 * kNbMax, method, panel_rows, q);
     if (r) return r;
     return gemm(c_, C_GEMM_SMALL, A_N, B_N, P_F64, i, pb, pb, Vq, i, Tq, pb, Wtq, i, 1.0, 0.0, q);
   };
@@ -692,7 +705,8 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
     const int pr = std::max(0, std::min(pb, n - w - 1 - c));
     const int c0 = c + w, jr = n - c0;
     int r = panel_factor(c_, true, A + c + (int64_t)c0 * lda, lda, jr, pr, Up, jr, taup + c, Tp, pr,
-                         pw, counters + 2 * it + 1, pflags + 4 * it + 2, method, panel_rows, q);
+                         pw, counters + 2 * it + 1, pflags + 4 * it + 2,
+                         pstruct + (size_t)(2 * it + 1) * 2 * kNbMax, method, panel_rows, q);
     if (r) return r;
     return gemm(c_, C_GEMM_SMALL, A_N, B_N, P_F64, jr, pr, pr, Up, jr, Tp, pr, Wtp, jr, 1.0, 0.0, q);
   };

@@ -100,12 +100,12 @@ int launch_panel(bool rowmajor, const PanelDesc &d, int nwg, hipStream_t s);
 int launch_larft(const double *S, int ldS, const double *tau, int nb, double *T, int ldT,
                  hipStream_t s, const int *gate = nullptr, int gate_val = 0);
 int launch_chol_inv(const double *G, int ldg, int b, double rel, double *R, double *Rinv, int *flag,
-                    int check_structure, hipStream_t s);
+                    const int *structure, hipStream_t s);
 int launch_recon(const double *Qtop, int ldq, int b, double *V, int64_t ldv, double *T, int ldt,
                  double *tau, double *Uinv, double *sgn, double *Uscr, const int *flag,
                  hipStream_t s);
-int launch_lower_nonzero(const double *P, int64_t ldp, int rowmajor, int m, int b, int *count,
-                         hipStream_t s);
+int launch_panel_structure(const double *P, int64_t ldp, int rowmajor, int m, int b,
+                           int *structure, hipStream_t s);
 int launch_panel_finalize(double *P, int64_t ldp, int rowmajor, int m, int b, const double *V,
                           int64_t ldv, const double *Rh0, const double *sgn, const int *flag,
                           hipStream_t s);

@@ -28,10 +28,13 @@
 // the solve for T are independent column by column (row by row for T), so they
 // run on one workgroup per 16-wide slab with the triangular operand in LDS.
 //
-// Rank-deficient or structurally reduced panels: a pivot of the first
-// Cholesky below rel * (original diagonal), or a panel with no nonzero below
-// its diagonal, raises a device flag; the remaining kernels of this path then
-// return at once and the exact per-column Householder kernel takes the panel.
+// Rank-deficient panels and panels with a structurally zero column: a pivot
+// of the first Cholesky below rel * (original diagonal), or a column k whose
+// part below the diagonal is exactly zero by the panel's sparsity structure,
+// raises a device flag; the remaining kernels of this path then return at once
+// and the exact per-column Householder kernel takes the panel.  (For such a
+// column the Householder convention sets tau = 0, H = I; the reconstruction
+// would return the other valid reflector, tau = 2.)
 #include "common.hpp"
 
 namespace br {
@@ -106,6 +109,7 @@ struct Bcast {
   double pr[2][kTE];            // reciprocals of its pivots
   double d0[kNbMax];            // original diagonal (Cholesky breakdown test)
   double sg[kNbMax];            // LU signs
+  int lz[kNbMax];               // structure check: last nonzero row of each column
   int bad;
 };
 
@@ -371,24 +375,50 @@ __device__ __forceinline__ void blk_lu_sign(Tile &T, const TileCtx &c, Bcast &s,
 
 // ---------------------------------------------------------------------------
 // kernel A: R = chol(G) (full column-major, zeros below); R^-1 follows in
-// k_trinv
-// flag[0]: raised on breakdown; flag[1]: nonzero count of the panel's
-// strictly lower part (0 = structurally reduced panel)
+// k_trinv.  flag[0] is raised on breakdown, and, when `structure` is given
+// (the output of k_panel_structure for this panel), if some column k has no
+// nonzero strictly below its diagonal once the earlier columns' reflectors are
+// applied: that holds exactly when every column j <= k has its last nonzero
+// at or above row k (the reflectors of columns 0..k-1 then only mix rows
+// 0..k).  For a panel taller than b every column has rows below its diagonal.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kRT) void k_chol(const double *G, int ldg, int b, double rel,
-                                              double *R, int *flag, int check_structure) {
+                                              double *R, int *flag, const int *structure) {
   __shared__ Bcast s;
   __builtin_amdgcn_s_setprio(kPrioPanel);
-  // the flags are read before, and tested after, the matrix loads so that the
-  // two memory latencies overlap
-  const int f0 = flag[0], f1 = flag[1];
+  // the flag and structure are read before, and tested after, the matrix
+  // loads so that the memory latencies overlap
+  const int f0 = flag[0];
   const TileCtx c = tile_ctx();
+  int lz = kNbMax;  // columns beyond b never count
+  if (structure && c.t < b) lz = structure[kNbMax + c.t] ? kNbMax : structure[c.t];
   Tile T;
   tile_load(T, c, s, G, ldg, b);
   if (f0) return;
-  if (check_structure && f1 == 0) {
-    if (threadIdx.x == 0) flag[0] = 1;
-    return;
+  if (structure) {
+    if (c.t < kNbMax) s.lz[c.t] = lz;
+    __syncthreads();
+    if (c.t < 64) {
+      // wave 0: lane l holds columns 2l, 2l+1; prefix maximum over columns
+      const int k0 = 2 * c.t, k1 = k0 + 1;
+      const int p0 = s.lz[k0], p1 = max(p0, s.lz[k1]);
+      int inc = p1;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(inc, off);
+        if (c.t >= off) inc = max(inc, y);
+      }
+      int ex = __shfl_up(inc, 1);
+      if (c.t == 0) ex = 0;
+      const bool zero_col = (k0 < b && max(ex, p0) <= k0) || (k1 < b && max(ex, p1) <= k1);
+      const bool any = __any(zero_col);
+      if (c.t == 0) s.bad = any ? 1 : 0;
+    }
+    __syncthreads();
+    if (s.bad) {
+      if (c.t == 0) flag[0] = 1;
+      return;
+    }
   }
   if (c.bi == c.bj) {
 #pragma unroll
@@ -705,51 +735,72 @@ __global__ void k_panel_finalize(double *P, int64_t ldp, int rowmajor, int m, in
   }
 }
 
-// Count (per workgroup, at most once) nonzero entries strictly below the
-// diagonal of the panel.  A panel with none is already reduced: every column
-// has sigma = 0 and the Householder convention gives tau = 0, which the
-// reconstruction cannot reproduce, so such panels take the per-column path.
-__global__ void k_lower_nonzero(const double *P, int64_t ldp, int rowmajor, int m, int b,
-                                int *count) {
-  __shared__ int found;
+// Sparsity structure of the m x b panel below its diagonal, for the check of
+// k_chol: structure[k] = the last row r < b with r > k and P(r, k) != 0 (0 if
+// none), structure[kNbMax + k] = 1 when column k has a nonzero in some row
+// >= b.  Both zero on entry; every workgroup reduces its share in LDS and then
+// raises the global entries (atomic maximum for the rows, plain stores of one
+// value for the flags).  The loads are issued four at a time.
+__global__ void k_panel_structure(const double *P, int64_t ldp, int rowmajor, int m, int b,
+                                  int *structure) {
+  __shared__ int s_top[kNbMax], s_deep[kNbMax];
   __builtin_amdgcn_s_setprio(kPrioPanel);
-  if (threadIdx.x == 0) found = 0;
+  const int t = threadIdx.x;
+  for (int k = t; k < kNbMax; k += blockDim.x) {
+    s_top[k] = 0;
+    s_deep[k] = 0;
+  }
   __syncthreads();
   const int64_t total = (int64_t)m * b;
-  int mine = 0;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    int r, k;
-    if (!rowmajor) {
-      r = (int)(idx % m);
-      k = (int)(idx / m);
-    } else {
-      k = (int)(idx % b);
-      r = (int)(idx / b);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  constexpr int U = 4;
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x + t; base < total; base += U * stride) {
+    double v[U];
+    int r[U], k[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t idx = base + u * stride;
+      const int64_t ic = idx < total ? idx : 0;  // clamped: the value is ignored
+      if (!rowmajor) {
+        r[u] = (int)(ic % m);
+        k[u] = (int)(ic / m);
+      } else {
+        k[u] = (int)(ic % b);
+        r[u] = (int)(ic / b);
+      }
+      v[u] = rowmajor ? P[k[u] + (int64_t)r[u] * ldp] : P[r[u] + (int64_t)k[u] * ldp];
+      if (idx >= total) v[u] = 0.0;
     }
-    if (r > k) {
-      const double v = rowmajor ? P[k + (int64_t)r * ldp] : P[r + (int64_t)k * ldp];
-      if (v != 0.0) mine = 1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (v[u] != 0.0 && r[u] > k[u]) {
+        if (r[u] >= b) s_deep[k[u]] = 1;
+        else atomicMax(&s_top[k[u]], r[u]);
+      }
     }
   }
-  if (mine) found = 1;
   __syncthreads();
-  if (threadIdx.x == 0 && found) atomicAdd(count, 1);
+  for (int k = t; k < b; k += blockDim.x) {
+    if (s_top[k] > 0) atomicMax(&structure[k], s_top[k]);
+    if (s_deep[k]) structure[kNbMax + k] = 1;
+  }
 }
 
-int launch_lower_nonzero(const double *P, int64_t ldp, int rowmajor, int m, int b, int *count,
-                         hipStream_t s) {
+int launch_panel_structure(const double *P, int64_t ldp, int rowmajor, int m, int b,
+                           int *structure, hipStream_t s) {
   const int64_t total = (int64_t)m * b;
   int blocks = (int)((total + 1023) / 1024);
   if (blocks > 512) blocks = 512;
-  hipLaunchKernelGGL(k_lower_nonzero, dim3(blocks), dim3(256), 0, s, P, ldp, rowmajor, m, b, count);
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_panel_structure, dim3(blocks), dim3(256), 0, s, P, ldp, rowmajor, m, b,
+                     structure);
   BR_HIP_CHECK(hipGetLastError());
   return 0;
 }
 
 int launch_chol_inv(const double *G, int ldg, int b, double rel, double *R, double *Rinv, int *flag,
-                    int check_structure, hipStream_t s) {
-  hipLaunchKernelGGL(k_chol, dim3(1), dim3(kRT), 0, s, G, ldg, b, rel, R, flag, check_structure);
+                    const int *structure, hipStream_t s) {
+  hipLaunchKernelGGL(k_chol, dim3(1), dim3(kRT), 0, s, G, ldg, b, rel, R, flag, structure);
   BR_HIP_CHECK(hipGetLastError());
   hipLaunchKernelGGL(k_trinv, dim3((b + kSW - 1) / kSW), dim3(kST), 0, s, R, b, b, Rinv, b,
                      (const int *)flag);

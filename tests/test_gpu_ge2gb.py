@@ -55,6 +55,31 @@ def test_ge2gb_banded_input_is_exact(bandred):
     assert np.array_equal(Ag, A)
 
 
+@pytest.mark.parametrize("lookahead", [True, False], ids=["lookahead", "serial"])
+def test_ge2gb_reduced_later_panels_fall_back(bandred, orc, lookahead):
+    """A = [[A1, 0], [0, D]], D diagonal: the left panels from column s and
+    the right panels from row s - w have no nonzero off their band, are
+    flagged and take the gated per-column path (tau = 0 as in the oracle)."""
+    m, n, w, s = 700, 500, 32, 256
+    A = np.zeros((m, n))
+    A[:s, :s] = inputs.ge_normal(s, s, 91)
+    k = np.arange(n - s)
+    A[s + k, s + k] = inputs.ge_normal(n - s, 1, 92)[:, 0]
+    print(f"case ge2gb reduced later panels m={m} n={n} w={w} s={s} lookahead={lookahead}",
+          flush=True)
+    Ad, _ = to_device_colmajor(A)
+    tq, tp = bandred.ge2gb(Ad, w, w, lookahead=lookahead)
+    torch.cuda.synchronize()
+    Ag, tqg, tpg = Ad.cpu().numpy(), tq.cpu().numpy(), tp.cpu().numpy()
+    Ao, tqo, tpo = orc.ge2gb(A, w)
+    assert np.all(tqo[s:] == 0.0) and np.all(tpo[s - w:] == 0.0)
+    assert np.all(tqg[s:] == 0.0) and np.all(tpg[s - w:] == 0.0)
+    db, dl, dr, dq, dp = ge_compare(Ag, tqg, tpg, Ao, tqo, tpo, w)
+    tol = 1e-14 * m
+    assert db <= tol * np.linalg.norm(A), db
+    assert max(dl, dr, dq, dp) <= tol, (dl, dr, dq, dp)
+
+
 @pytest.mark.parametrize("m,n,w", [(1200, 900, 64), (700, 700, 32), (1000, 1000, 128)])
 def test_ge2gb_lookahead_is_bit_identical_to_serial(bandred, m, n, w):
     """The look-ahead only reorders independent launches (panels on the

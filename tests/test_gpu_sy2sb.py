@@ -105,6 +105,30 @@ def test_rank_deficient_panel_falls_back(bandred, orc):
     assert db <= tol * np.linalg.norm(A) and dr <= tol and dt <= tol, (db, dr, dt)
 
 
+@pytest.mark.parametrize("s", [300, 320])
+@pytest.mark.parametrize("lookahead", [True, False], ids=["lookahead", "serial"])
+def test_reduced_later_panels_fall_back(bandred, orc, lookahead, s):
+    """Block diagonal A = diag(A1, D), D diagonal: from column s - w on no
+    column has a nonzero below the band, so the panels there (later panels,
+    factored on the look-ahead stream) are flagged and take the gated
+    per-column path, which gives tau = 0 exactly as the oracle does.  With
+    s = 320 the panel at column 256 has full rank but its last column is zero
+    below its diagonal (tau = 0 by the Householder convention, which the
+    structure check routes to the per-column path)."""
+    n, w = 600, 32
+    A = np.zeros((n, n))
+    A[:s, :s] = inputs.sym_normal(s, 41)
+    A[s:, s:] = np.diag(np.diag(inputs.sym_normal(n - s, 42)))
+    print(f"case sy2sb reduced later panels n={n} w={w} s={s} lookahead={lookahead}", flush=True)
+    Ag, tg, _ = _run(bandred, A, w, w, lookahead=lookahead)
+    Ao, to = orc.sy2sb(A, w)
+    assert np.all(to[s - w:] == 0.0)
+    assert np.all(tg[s - w:] == 0.0)
+    db, dr, dt = sy_compare(np.tril(Ag), tg, np.tril(Ao), to, w)
+    tol = 1e-14 * n
+    assert db <= tol * np.linalg.norm(A) and dr <= tol and dt <= tol, (db, dr, dt)
+
+
 def test_numerically_dependent_columns(bandred):
     """Two proportional columns: the later one becomes zero up to rounding
     after the earlier reflectors, so its reflector is set by rounding noise
