@@ -14,7 +14,7 @@ the same matrix, accuracy of the timed result, the dominant kernel against
 the FP64 matrix-core peak, and the CPU oracle timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-       [--no-forms] [--no-cpu-baseline] [--profile-only]
+       [--no-forms] [--no-cpu-baseline] [--profile-only] [--roofline-only]
 """
 from __future__ import annotations
 
@@ -64,6 +64,41 @@ def pmc_traffic(cls, workload):
         return None
     cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
     return val if cur.startswith(sha) else None
+
+
+def serial_call(br, A, is_ge, w, b):
+    """One FP64 reduction without look-ahead: every kernel alone on the GPU."""
+    if is_ge:
+        br.ge2gb(A, w, b, prec="fp64", lookahead=False)
+    else:
+        br.sy2sb(A, w, b, prec="fp64", lookahead=False)
+
+
+def serial_roofline(br, A, restore, is_ge, w, b, workload):
+    """Per-launch HIP events (on the stream each kernel runs on) over one
+    serial reduction.  The roofline entry is the contraction class with the
+    most device time; the panel classes (latency-bound single-workgroup and
+    tall-skinny kernels) are listed in "kernels" instead."""
+    import torch
+
+    restore()
+    torch.cuda.synchronize()
+    br.bandred_profile_enable(True)
+    serial_call(br, A, is_ge, w, b)
+    torch.cuda.synchronize()
+    prof_serial = br.bandred_profile_read()
+    br.bandred_profile_enable(False)
+    mfma_cls = ("symm", "syr2k", "gemm_update")
+    dom = max((k for k in prof_serial if k in mfma_cls and prof_serial[k]["launches"]),
+              key=lambda k: prof_serial[k]["ms"])
+    d = prof_serial[dom]
+    achieved = d["flops"] / (d["ms"] / 1e3) / 1e12
+    roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_TFLOPS["fp64"],
+                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["fp64"],
+                "traffic": pmc_traffic(dom, workload),
+                "avg_launch_ms": d["ms"] / max(d["launches"], 1), "launches": d["launches"],
+                "flops_per_launch": d["flops"] / max(d["launches"], 1)}
+    return roofline, prof_serial
 
 
 def time_steps(run, restore, steps, stream):
@@ -325,6 +360,8 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="warm up and run the steps only (for rocprofv3)")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="one serial warm-up and the serial per-kernel step only (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only; this build has no multi-GPU path "
@@ -368,6 +405,15 @@ def main():
         return run
 
     run_eager = runner("fp64")
+    if args.roofline_only:
+        # the serial per-kernel step alone, after one serial warm-up: under
+        # rocprofv3 every launch of the trace is one the roofline figure covers
+        restore()
+        serial_call(br, A, is_ge, w, b)
+        torch.cuda.synchronize()
+        roofline, _ = serial_roofline(br, A, restore, is_ge, w, b, args.workload)
+        print(json.dumps({"metric": METRIC, "workload": args.workload, "roofline": roofline}))
+        return
     log(f"bench: warmup {args.warmup}")
     for _ in range(max(1, args.warmup)):
         restore()
@@ -416,30 +462,8 @@ def main():
     run_eager()  # per-launch events are recorded by eager calls only
     torch.cuda.synchronize()
     prof = br.bandred_profile_read()
-    # the same step without look-ahead: every kernel alone on the GPU
-    restore()
-    torch.cuda.synchronize()
-    br.bandred_profile_enable(True)
-    if is_ge:
-        br.ge2gb(A, w, b, prec="fp64")
-    else:
-        br.sy2sb(A, w, b, prec="fp64", lookahead=False)
-    torch.cuda.synchronize()
-    prof_serial = br.bandred_profile_read()
     br.bandred_profile_enable(False)
-    # the roofline entry is the contraction class with the most device time
-    # (serial step, every kernel alone); the panel classes, latency-bound
-    # single-workgroup and tall-skinny kernels, are listed in "kernels"
-    mfma_cls = ("symm", "syr2k", "gemm_update")
-    dom = max((k for k in prof_serial if k in mfma_cls and prof_serial[k]["launches"]),
-              key=lambda k: prof_serial[k]["ms"])
-    d = prof_serial[dom]
-    achieved = d["flops"] / (d["ms"] / 1e3) / 1e12
-    roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_TFLOPS["fp64"],
-                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["fp64"],
-                "traffic": pmc_traffic(dom, args.workload),
-                "avg_launch_ms": d["ms"] / max(d["launches"], 1), "launches": d["launches"],
-                "flops_per_launch": d["flops"] / max(d["launches"], 1)}
+    roofline, prof_serial = serial_roofline(br, A, restore, is_ge, w, b, args.workload)
     breakdown = {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
                      "tflops": (v["flops"] / (v["ms"] / 1e3) / 1e12) if v["ms"] > 0 and v["flops"] > 0 else None}
                  for k, v in prof.items() if v["launches"]}

@@ -1,4 +1,4 @@
-# Profiling helper (not a test; run under rocprofv3 --pmc): one SY2SB n=16384 w=b=128 on a symmetric N(0,1) matrix (no QR in the input
+# Profiling helper (not a test; run under rocprofv3 --pmc): one serial SY2SB n=16384 w=b=128 on a symmetric N(0,1) matrix (no QR in the input
 # generation), preceded by a plain 2 GiB device copy used to calibrate the
 # FETCH_SIZE / WRITE_SIZE counters
 import sys
@@ -14,6 +14,8 @@ B = torch.empty_like(A)
 torch.cuda.synchronize()
 B.copy_(A)          # calibration: reads and writes n*n*8 bytes
 torch.cuda.synchronize()
-tau = br.sy2sb(A, 128, 128)
+# the serial reduction (no look-ahead): its launches are the ones the bench's
+# roofline figure covers (every kernel alone on the GPU)
+tau = br.sy2sb(A, 128, 128, lookahead=False)
 torch.cuda.synchronize()
 print("done", float(tau[:4].sum()))
