@@ -1,0 +1,133 @@
+"""GPU parity at the full sizes the bench times, in the bench's launch
+configuration (look-ahead, the whole reduction replayed from a HIP graph), on
+sampled outputs the oracle can compute: the reflector columns of the first
+panels, from an oracle run over only those columns (the first k columns of
+the result are final after k steps, since later reflectors act on rows and
+columns beyond them).  The sampled columns depend on the trailing updates of
+the first iterations, which at these sizes run as chunked launches beside the
+look-ahead panel.  Properties that hold at any size (backward error,
+orthogonality, by random probes) are checked on the whole result.
+
+Tolerances as in the small parity tests: 1e-14 * n * ||A||_F for band entries,
+1e-14 * n for v and tau; backward error and orthogonality 1e-14 * n."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1709_00302_amd import inputs, metrics
+
+pytestmark = pytest.mark.gpu
+
+
+def _graph(run, restore):
+    """Eager call (reserves the workspace), then the call captured in a HIP
+    graph on a side stream and replayed once on the restored input, as the
+    bench times it; returns the replay's output (and the graph, kept alive)."""
+    restore()
+    run({})  # eager: reserves the workspace
+    torch.cuda.synchronize()
+    restore()
+    torch.cuda.synchronize()
+    out = {}
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cs):
+        with torch.cuda.graph(g, stream=cs):
+            run(out)
+    torch.cuda.synchronize()
+    restore()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    return out, g
+
+
+def test_sy2sb_full_size_graph_replay(bandred, orc):
+    name = "sy2sb_n16384_w128"
+    print(f"case {name}: building the input on the GPU", flush=True)
+    p = inputs.make_on_device(name, device="cuda")
+    A0, n, w, b = p["A"], p["n"], p["w"], p["b"]
+    A = torch.empty_like(A0)
+    A.copy_(A0)
+
+    def restore():
+        A.copy_(A0)
+
+    def run(out):
+        out["tau"] = bandred.sy2sb(A, w, b)
+
+    print(f"case {name}: graph replay", flush=True)
+    out, _g = _graph(run, restore)
+    tau = out["tau"].clone()
+    err = metrics.sy2sb_errors(A0, torch.tril(A), tau, w, eig=False)
+    print(f"case {name}: backward {err['backward']:.3e} orth {err.get('orth')}", flush=True)
+    assert err["backward"] <= 1e-14 * n, err
+    if err.get("orth") is not None:
+        assert err["orth"] <= 1e-14 * n, err
+
+    k = 3 * b + 16  # the first three panels and part of the fourth
+    print(f"case {name}: oracle on the first {k} reflector columns", flush=True)
+    Ah = A0.cpu().numpy()
+    Ao, to = orc.sy2sb(Ah, w, ncols=k)
+    G = A[:, :k].cpu().numpy()
+    O = Ao[:, :k]
+    tg = tau[:k].cpu().numpy()
+    i = np.arange(n)[:, None]
+    j = np.arange(k)[None, :]
+    band = (i - j >= 0) & (i - j <= w)
+    refl = i - j > w
+    nA = np.linalg.norm(Ah)  # the input holds both triangles
+    db = np.abs(G - O)[band].max()
+    dv = np.abs(G - O)[refl].max()
+    dt = np.abs(tg - to[:k]).max()
+    print(f"case {name}: band {db:.3e} v {dv:.3e} tau {dt:.3e}", flush=True)
+    tol = 1e-14 * n
+    assert db <= tol * nA and dv <= tol and dt <= tol, (db, dv, dt)
+
+
+def test_ge2gb_full_size_graph_replay(bandred, orc):
+    name = "ge2gb_24576x12288_w128"
+    print(f"case {name}: building the input on the GPU", flush=True)
+    p = inputs.make_on_device(name, device="cuda")
+    A0, m, n, w, b = p["A"], p["m"], p["n"], p["w"], p["b"]
+    A = torch.empty_like(A0)
+    A.copy_(A0)
+
+    def restore():
+        A.copy_(A0)
+
+    def run(out):
+        out["tau"] = bandred.ge2gb(A, w, b)
+
+    print(f"case {name}: graph replay", flush=True)
+    out, _g = _graph(run, restore)
+    tq, tp = (t.clone() for t in out["tau"])
+    err = metrics.ge2gb_errors(A0, A, tq, tp, w, svd=False)
+    print(f"case {name}: backward {err['backward']:.3e}", flush=True)
+    assert err["backward"] <= 1e-14 * m, err
+
+    k = 2 * b + 8  # the first two steps' panels and part of the third
+    print(f"case {name}: oracle on the first {k} steps", flush=True)
+    Ah = A0.cpu().numpy()
+    Ao, tqo, tpo = orc.ge2gb(Ah, w, ncols=k)
+    nA = np.linalg.norm(Ah)
+    tol = 1e-14 * m
+    # columns 0..k-1 and rows 0..k-1 are final after k steps
+    Gc, Oc = A[:, :k].cpu().numpy(), Ao[:, :k]
+    Gr, Or = A[:k, :].cpu().numpy(), Ao[:k, :]
+    ic = np.arange(m)[:, None]
+    jc = np.arange(k)[None, :]
+    band_c = (jc - ic >= 0) & (jc - ic <= w)
+    ir = np.arange(k)[:, None]
+    jr = np.arange(n)[None, :]
+    band_r = (jr - ir >= 0) & (jr - ir <= w)
+    db = max(np.abs(Gc - Oc)[band_c].max(), np.abs(Gr - Or)[band_r].max())
+    dl = np.abs(Gc - Oc)[ic > jc].max()          # left reflectors below the diagonal
+    dr = np.abs(Gr - Or)[jr - ir > w].max()      # right reflectors right of the band
+    dq = np.abs(tq[:k].cpu().numpy() - tqo[:k]).max()
+    dp = np.abs(tp[:k].cpu().numpy() - tpo[:k]).max()
+    print(f"case {name}: band {db:.3e} left {dl:.3e} right {dr:.3e} tauq {dq:.3e} taup {dp:.3e}",
+          flush=True)
+    assert db <= tol * nA, db
+    assert max(dl, dr, dq, dp) <= tol, (dl, dr, dq, dp)
