@@ -131,3 +131,64 @@ def test_ge2gb_full_size_graph_replay(bandred, orc):
           flush=True)
     assert db <= tol * nA, db
     assert max(dl, dr, dq, dp) <= tol, (dl, dr, dq, dp)
+
+
+def test_batched_full_size_graph_replay(bandred, orc):
+    """The batched workload as the bench times it (2048 matrices of orders
+    64 .. 1024, w = b = 16, one persistent launch replayed from a HIP graph);
+    eight matrices spread over the size range, the smallest and the largest
+    among them, compared with the oracle element by element."""
+    name = "batched_2048_w16"
+    print(f"case {name}: building the input on the GPU", flush=True)
+    p = inputs.make_on_device(name, device="cuda")
+    w, b = p["w"], p["b"]
+    sizes = [int(x) for x in p["sizes"]]
+    offs = [int(x) for x in p["offsets"]]
+    flat0 = p["flat"]
+    flat = flat0.clone()
+    count = len(sizes)
+    ptrs = [flat.data_ptr() + 8 * o for o in offs]
+    tl = [max(n - w, 1) for n in sizes]
+    taus = torch.zeros(sum(tl), dtype=torch.float64, device="cuda")
+    toffs = np.concatenate([[0], np.cumsum(tl)])[:-1]
+    tptrs = [taus.data_ptr() + 8 * int(o) for o in toffs]
+
+    def call(s):
+        rc = bandred.bandred_sy2sb_batched(count, sizes, w, b, ptrs, sizes, tptrs, 0, s)
+        assert rc == 0, bandred.status_string(rc)
+
+    stream = torch.cuda.current_stream()
+    call(stream.cuda_stream)  # eager: uploads the matrix table
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(stream)
+    with torch.cuda.stream(cs):
+        with torch.cuda.graph(g, stream=cs):
+            call(cs.cuda_stream)
+    torch.cuda.synchronize()
+    flat.copy_(flat0)
+    taus.zero_()
+    torch.cuda.synchronize()
+    print(f"case {name}: graph replay", flush=True)
+    g.replay()
+    torch.cuda.synchronize()
+    order = np.argsort(sizes)
+    pick = sorted(set(int(order[i]) for i in np.linspace(0, count - 1, 8).round().astype(int)))
+    for k in pick:
+        n, o = sizes[k], offs[k]
+        A = flat0[o:o + n * n].view(n, n).T.cpu().numpy()  # column-major view
+        Ag = flat[o:o + n * n].view(n, n).T.cpu().numpy()
+        tg = taus[int(toffs[k]):int(toffs[k]) + max(n - w, 0)].cpu().numpy()
+        Ao, to = orc.sy2sb(A, w)
+        i = np.arange(n)[:, None]
+        j = np.arange(n)[None, :]
+        band = (i - j >= 0) & (i - j <= w)
+        refl = i - j > w
+        db = np.abs(Ag - Ao)[band].max()
+        dv = np.abs(Ag - Ao)[refl].max() if n > w + 1 else 0.0
+        dt = np.abs(tg - to).max() if n > w else 0.0
+        print(f"case {name}: matrix {k} n={n}: band {db:.3e} v {dv:.3e} tau {dt:.3e}", flush=True)
+        tol = 1e-14 * n
+        nA = np.linalg.norm(np.tril(A) + np.tril(A, -1).T)  # the symmetric matrix the call reduces
+        assert db <= tol * nA and dv <= tol and dt <= tol, (k, n, db, dv, dt)
