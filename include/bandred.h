@@ -64,7 +64,8 @@ typedef struct {
                          0: one stream, strictly sequential (debug / comparison) */
   int panel_rows;     /* rows per workgroup of the per-column panel kernel; 0 = automatic */
   int panel_method;   /* 0 (default) or 2: CholeskyQR2 + Householder reconstruction, with the
-                         per-column kernel as fallback for rank-deficient panels;
+                         per-column kernel as fallback for rank-deficient panels and
+                         panels with a column that is zero below its diagonal;
                          1: per-column Householder kernel only */
   int reserved[5];    /* must be zero */
 } bandred_opts_t;

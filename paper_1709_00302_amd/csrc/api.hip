@@ -265,9 +265,10 @@ static int gemm(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int 
 
 // A2(lower, columns [c0, c1)) -= W V^T + V W^T with WV = [W | V] (j x 2pb).
 static int syr2k(Ctx &cx, int prec, int j, int pb, const double *WV, int64_t ldwv, double *A2,
-                 int64_t lda, int c0, int c1, hipStream_t s) {
+                 int64_t lda, int c0, int c1, hipStream_t s, int lds_pad = 0) {
   if (c1 <= c0) return 0;
   GemmDesc d{};
+  d.lds_pad = lds_pad;
   d.M = j; d.N = j; d.K = 2 * pb;
   d.A = WV; d.lda = ldwv; d.B = WV; d.ldb = ldwv;
   d.C = A2; d.ldc = lda;
@@ -295,6 +296,14 @@ static int syr2k(Ctx &cx, int prec, int j, int pb, const double *WV, int64_t ldw
 // save), each at least two full rounds of resident 128 x 128 workgroups.
 // Every element is still computed by one tile in the same order.
 constexpr int kMaxChunks = 3;
+// Below a trailing order of 8192 the panel beside the SYR2K is the longer of
+// the two by a wider margin; there the SYR2K launches reserve 20 KB of extra
+// LDS per workgroup, which leaves one of its 128 x 128 workgroups per CU (86 KB
+// of 160) and the rest of the CU to the panel's kernels that fit beside one
+// (measured: SY2SB n=8192 w=64 1.3% faster, n=16384 w=128 0.5%; applied at
+// every order the cap costs the large SYR2K launches more than it gains).
+constexpr int kSyr2kPadBelow = 8192;
+constexpr int kSyr2kPad = 20 * 1024;
 static int update_chunks(const DevState *st, int64_t tiles128) {
   const int64_t per = 4 * (int64_t)st->num_cu;  // two rounds of two workgroups per CU
   return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxChunks, tiles128 / per));
@@ -320,7 +329,8 @@ static int syr2k_chunked(Ctx &cx, int prec, int j, int pb, const double *WV, int
       hi = lo;
       while (hi < c1 && area(hi) < tot * k / nck) hi = std::min(c1, hi + 128);
     }
-    int rc = syr2k(cx, prec, j, pb, WV, ldwv, A2, lda, lo, hi, s);
+    int rc = syr2k(cx, prec, j, pb, WV, ldwv, A2, lda, lo, hi, s,
+                   j <= kSyr2kPadBelow ? kSyr2kPad : 0);
     if (rc) return rc;
     lo = hi;
   }

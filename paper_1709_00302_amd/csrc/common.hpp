@@ -53,6 +53,7 @@ struct GemmDesc {
   int64_t ldc2;
   int c2_trans;    // ... at (row, col) (ld ldc2), or transposed at (col, row)
   int prio;        // nonzero: the waves run at raised issue priority (panel products)
+  int lds_pad;     // extra LDS bytes reserved per workgroup (limits residency per CU)
 };
 
 // Wave issue priority of the panel kernels.  The panel of the next step runs

@@ -477,7 +477,7 @@ static int launch_t(const GemmDesc &d, int ksplit, hipStream_t s) {
     if (d.M <= 0 || d.N <= 0) return 0;
     grid = dim3((d.M + BM - 1) / BM, (d.N + BN - 1) / BN, ksplit);
   }
-  hipLaunchKernelGGL((k_gemm<BM, BN, OPA, OPB, EPI, PREC>), grid, dim3(kThreads), 0, s, d);
+  hipLaunchKernelGGL((k_gemm<BM, BN, OPA, OPB, EPI, PREC>), grid, dim3(kThreads), d.lds_pad, s, d);
   return 0;
 }
 
