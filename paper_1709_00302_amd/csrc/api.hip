@@ -203,7 +203,7 @@ static int gemm(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int 
                 const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
                 int64_t ldc, double alpha, double beta, hipStream_t s,
                 const int *gate = nullptr, int gate_val = 0, double *C2 = nullptr,
-                int64_t ldc2 = 0, int c2_trans = 0) {
+                int64_t ldc2 = 0, int c2_trans = 0, int lds_pad = 0) {
   if (M <= 0 || N <= 0) return 0;
   if (K <= 0) {
     if (beta == 1.0) return 0;
@@ -215,6 +215,7 @@ static int gemm(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int 
   d.alpha = alpha; d.beta = beta;
   d.gate = gate; d.gate_val = gate_val;
   d.C2 = C2; d.ldc2 = ldc2; d.c2_trans = c2_trans;
+  d.lds_pad = lds_pad;
   d.prio = (cls == C_PANEL || cls == C_GEMM_SMALL) ? 1 : 0;
   const int bm = (M <= 64 && N <= 64) ? 64 : 128;
   const int tiles = ((M + bm - 1) / bm) * ((N + bm - 1) / bm);
@@ -296,12 +297,13 @@ static int syr2k(Ctx &cx, int prec, int j, int pb, const double *WV, int64_t ldw
 // save), each at least two full rounds of resident 128 x 128 workgroups.
 // Every element is still computed by one tile in the same order.
 constexpr int kMaxChunks = 3;
-// Below a trailing order of 8192 the panel beside the SYR2K is the longer of
-// the two by a wider margin; there the SYR2K launches reserve 20 KB of extra
-// LDS per workgroup, which leaves one of its 128 x 128 workgroups per CU (86 KB
-// of 160) and the rest of the CU to the panel's kernels that fit beside one
-// (measured: SY2SB n=8192 w=64 1.3% faster, n=16384 w=128 0.5%; applied at
-// every order the cap costs the large SYR2K launches more than it gains).
+// Below a trailing order (GE2GB: update rows) of 8192 the panel beside the
+// update is the longer of the two by a wider margin; there the update's
+// launches reserve 20 KB of extra LDS per workgroup, which leaves one of its
+// 128 x 128 workgroups per CU (86 KB of 160) and the rest of the CU to the
+// panel's kernels that fit beside one (measured: SY2SB n=8192 w=64 1.3%
+// faster, n=16384 w=128 0.5%, GE2GB 8192^2 w=64 1.2%; applied at every order
+// the cap costs the large updates more than it gains).
 constexpr int kSyr2kPadBelow = 8192;
 constexpr int kSyr2kPad = 20 * 1024;
 static int update_chunks(const DevState *st, int64_t tiles128) {
@@ -350,7 +352,8 @@ static int gemm_chunked(Ctx &cx, int cls, int opa, int opb, int prec, int M, int
     if (n1 <= n0) continue;
     const double *Bk = (opb == B_N) ? B + (int64_t)n0 * ldb : B + n0;
     int rc = gemm(cx, cls, opa, opb, prec, M, n1 - n0, K, A, lda, Bk, ldb,
-                  C + (int64_t)n0 * ldc, ldc, alpha, beta, s);
+                  C + (int64_t)n0 * ldc, ldc, alpha, beta, s, nullptr, 0, nullptr, 0, 0,
+                  M <= kSyr2kPadBelow ? kSyr2kPad : 0);
     if (rc) return rc;
     n0 = n1;
   }
