@@ -304,8 +304,8 @@ constexpr int kMaxChunks = 3;
 // panel's kernels that fit beside one (measured: SY2SB n=8192 w=64 1.3%
 // faster, n=16384 w=128 0.5%, GE2GB 8192^2 w=64 1.2%; applied at every order
 // the cap costs the large updates more than it gains).
-constexpr int kSyr2kPadBelow = 8192;
-constexpr int kSyr2kPad = 20 * 1024;
+constexpr int kUpdateCapBelow = 8192;
+constexpr int kUpdateCapLds = 20 * 1024;
 static int update_chunks(const DevState *st, int64_t tiles128) {
   const int64_t per = 4 * (int64_t)st->num_cu;  // two rounds of two workgroups per CU
   return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxChunks, tiles128 / per));
@@ -332,7 +332,7 @@ static int syr2k_chunked(Ctx &cx, int prec, int j, int pb, const double *WV, int
       while (hi < c1 && area(hi) < tot * k / nck) hi = std::min(c1, hi + 128);
     }
     int rc = syr2k(cx, prec, j, pb, WV, ldwv, A2, lda, lo, hi, s,
-                   j <= kSyr2kPadBelow ? kSyr2kPad : 0);
+                   j <= kUpdateCapBelow ? kUpdateCapLds : 0);
     if (rc) return rc;
     lo = hi;
   }
@@ -353,7 +353,7 @@ static int gemm_chunked(Ctx &cx, int cls, int opa, int opb, int prec, int M, int
     const double *Bk = (opb == B_N) ? B + (int64_t)n0 * ldb : B + n0;
     int rc = gemm(cx, cls, opa, opb, prec, M, n1 - n0, K, A, lda, Bk, ldb,
                   C + (int64_t)n0 * ldc, ldc, alpha, beta, s, nullptr, 0, nullptr, 0, 0,
-                  M <= kSyr2kPadBelow ? kSyr2kPad : 0);
+                  M <= kUpdateCapBelow ? kUpdateCapLds : 0);
     if (rc) return rc;
     n0 = n1;
   }
