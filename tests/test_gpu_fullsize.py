@@ -192,3 +192,29 @@ def test_batched_full_size_graph_replay(bandred, orc):
         tol = 1e-14 * n
         nA = np.linalg.norm(np.tril(A) + np.tril(A, -1).T)  # the symmetric matrix the call reduces
         assert db <= tol * nA and dv <= tol and dt <= tol, (k, n, db, dv, dt)
+
+
+@pytest.mark.parametrize("kind,m,n,w", [("sy", 9000, 9000, 128), ("ge", 6144, 6144, 128)])
+def test_lookahead_bit_identical_with_chunked_updates(bandred, kind, m, n, w):
+    """At these sizes the updates beside the look-ahead panel run as two
+    column-chunk launches in the first iterations (and below order 8192 with
+    the one-workgroup-per-CU reservation); the serial order runs each update
+    as one launch.  Every element is computed by one tile in the same k order
+    either way, so the two results are identical bit for bit."""
+    print(f"case lookahead chunked {kind} m={m} n={n} w={w}", flush=True)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(77)
+    Z = torch.randn(n, m, generator=g, device="cuda", dtype=torch.float64).T  # column-major m x n
+    outs = []
+    for la in (True, False):
+        A = Z.clone(memory_format=torch.preserve_format)
+        if kind == "sy":
+            tau = bandred.sy2sb(A, w, w, lookahead=la)
+            res = (torch.tril(A).cpu(), tau.cpu())
+        else:
+            tq, tp = bandred.ge2gb(A, w, w, lookahead=la)
+            res = (A.cpu(), tq.cpu(), tp.cpu())
+        torch.cuda.synchronize()
+        outs.append(res)
+    for x, y in zip(*outs):
+        assert torch.equal(x, y)
