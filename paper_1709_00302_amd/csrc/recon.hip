@@ -18,7 +18,8 @@
 // O(b^3) factorisations (Cholesky, LU) run in one workgroup of 1024 threads:
 // each thread keeps a 4 x 4 tile of the b x b matrix in registers (32 x 32
 // tiles cover b = 128; sizes below 128 are padded with the identity, which
-// every operation below leaves invariant).  They are blocked by 4 and take one
+// every operation below leaves invariant; tiles wholly inside the padding are
+// neither updated nor stored).  They are blocked by 4 and take one
 // workgroup barrier per block step: the diagonal block and its block row are
 // handled by the wave that owns them (broadcasts from the diagonal tile's
 // lane), the block row and column are published through LDS, and every
@@ -206,7 +207,7 @@ __device__ __forceinline__ bool blk_chol(Tile &T, const TileCtx &c, Bcast &s, in
   prio_next(c, -1);
   for (int kb = 0; kb < nblk; ++kb) {
     const int buf = kb & 1;
-    if (c.bi == kb && c.bj >= kb) {
+    if (c.bi == kb && c.bj >= kb && c.bj < nblk) {
       const int dl = diag_lane(kb);
       const bool diag = (c.bj == kb);
       bool ok = true;
@@ -235,7 +236,7 @@ __device__ __forceinline__ bool blk_chol(Tile &T, const TileCtx &c, Bcast &s, in
     }
     __syncthreads();
     prio_next(c, kb);
-    if (c.bi > kb && c.bj >= c.bi) {
+    if (c.bi > kb && c.bj >= c.bi && c.bj < nblk) {
 #pragma unroll
       for (int l = 0; l < kTE; ++l) {
         double x[kTE], y[kTE];
@@ -284,7 +285,7 @@ __device__ __forceinline__ void blk_lu_sign(Tile &T, const TileCtx &c, Bcast &s,
   prio_next(c, -1);
   for (int kb = 0; kb < nblk; ++kb) {
     const int buf = kb & 1;
-    if (c.bi == kb && c.bj >= kb) {
+    if (c.bi == kb && c.bj >= kb && c.bj < nblk) {
       const int dl = diag_lane(kb);
       const bool diag = (c.bj == kb);
 #pragma unroll
@@ -322,7 +323,7 @@ __device__ __forceinline__ void blk_lu_sign(Tile &T, const TileCtx &c, Bcast &s,
           for (int q = 0; q < kTE; ++q) s.rb[buf][r][q][c.bj] = T.a[r][q];
       }
     }
-    if (c.bj == kb && c.bi > kb) {
+    if (c.bj == kb && c.bi > kb && c.bi < nblk) {
 #pragma unroll
       for (int r = 0; r < kTE; ++r)
 #pragma unroll
@@ -330,7 +331,7 @@ __device__ __forceinline__ void blk_lu_sign(Tile &T, const TileCtx &c, Bcast &s,
     }
     __syncthreads();
     prio_next(c, kb);
-    if (c.bi > kb && c.bj >= kb) {
+    if (c.bi > kb && c.bj >= kb && c.bi < nblk && c.bj < nblk) {
       // L_ik = A_ik U_kk^-1 from the published raw block
       double U[kTE * kTE], A[kTE][kTE];
 #pragma unroll
