@@ -34,6 +34,8 @@ WORKLOADS = {
     "sy2sb_n16384_w128": dict(kind="sym_known", n=16384, w=128, b=128, spectrum="graded", seed=3),
     "ge2gb_24576x12288_w128": dict(kind="ge_known", m=24576, n=12288, w=128, b=128, seed=4),
     "batched_2048_w16": dict(kind="batch", count=2048, w=16, b=16, seed=5),
+    # look-ahead Variant V1 (2b <= w: the next panel lies in A1, Sec. 2.2)
+    "sy2sb_n16384_w256": dict(kind="sym_normal", n=16384, w=256, b=128, seed=6),
 }
 
 
