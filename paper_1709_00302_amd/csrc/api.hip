@@ -228,7 +228,7 @@ static int gemm(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int 
     // workgroups as possible: the time goes as rounds x (k chunk), plus the
     // reduction of the partial sums (memory bound, about one k unit per
     // 2.5e6 elements of each partial)
-    const int maxks = K / 256;
+    const int maxks = K / (cls == C_PANEL ? 128 : 256);
     double best = 0.0;
     for (int c = 1; c <= maxks; ++c) {
       if ((size_t)c * M * N > cx.part_cap) break;
@@ -519,7 +519,7 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
   const int npan = (nref + b - 1) / b;
   const int jmax = n - w;      // rows of the first panel
   const size_t part_main = std::max<size_t>((size_t)8 * jmax * b, (size_t)256 * b * b);
-  const size_t part_pan = (size_t)(jmax / 256 + 2) * b * b;
+  const size_t part_pan = (size_t)(jmax / 128 + 2) * b * b;
   size_t need = 0;
   need += 2 * round_up((size_t)jmax * 2 * b * 8, 256);   // WV[2] = [W | V]
   need += 2 * round_up((size_t)jmax * b * 8, 256);       // Wt[2] = V T
@@ -659,7 +659,7 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
   if (rc) return rc;
   const int npan = (n + b - 1) / b;
   const size_t part_cap = std::max<size_t>((size_t)8 * m * b, (size_t)256 * b * b);
-  const size_t part_pan = (size_t)(m / 256 + 2) * b * b;
+  const size_t part_pan = (size_t)(m / 128 + 2) * b * b;
   size_t need = 0;
   need += 2 * round_up((size_t)m * b * 8, 256);       // Vq, Wtq
   need += 2 * round_up((size_t)n * b * 8, 256);       // Up, Wtp
