@@ -222,17 +222,22 @@ static int gemm(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int 
   // workgroups resident at once: two per CU for the 128 x 128 tiles (VGPRs
   // and LDS), four for the 64 x 64 ones
   const int slots = (bm == 128 ? 2 : 4) * cx.st->num_cu;
+  // k-chunk granularity: the panel's Gram products (beside the running update
+  // more, shorter workgroups finish sooner) take chunks of 128 rows, or of 64
+  // for outputs of one 64 x 64 tile (b <= 64), which need more splits to fill
+  // the chip
+  const int kg = (cls == C_PANEL && M <= 64 && N <= 64) ? 64 : 128;
   int ks = 1;
   if (tiles < slots && K > 512 && !C2) {  // (the second output needs a single pass)
     // split k so that the work runs in as few full rounds of resident
     // workgroups as possible: the time goes as rounds x (k chunk), plus the
     // reduction of the partial sums (memory bound, about one k unit per
     // 2.5e6 elements of each partial)
-    const int maxks = K / (cls == C_PANEL ? 128 : 256);
+    const int maxks = K / (cls == C_PANEL ? kg : 256);  // (kg = 128 or 64 for the panel)
     double best = 0.0;
     for (int c = 1; c <= maxks; ++c) {
       if ((size_t)c * M * N > cx.part_cap) break;
-      const int kc = (int)round_up((K + c - 1) / c, 128);
+      const int kc = (int)round_up((K + c - 1) / c, kg);
       const int kk = (K + kc - 1) / kc;
       const int rounds = (tiles * kk + slots - 1) / slots;
       const double cost =
@@ -252,7 +257,7 @@ static int gemm(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int 
     ProfScope ps(cls, flops, s);
     return launch_gemm(opa, opb, E_AXPBY, prec, d, 1, s);
   }
-  d.kchunk = (int)round_up((K + ks - 1) / ks, 128);
+  d.kchunk = (int)round_up((K + ks - 1) / ks, kg);
   ks = (K + d.kchunk - 1) / d.kchunk;
   d.part = cx.part;
   {
@@ -519,7 +524,7 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
   const int npan = (nref + b - 1) / b;
   const int jmax = n - w;      // rows of the first panel
   const size_t part_main = std::max<size_t>((size_t)8 * jmax * b, (size_t)256 * b * b);
-  const size_t part_pan = (size_t)(jmax / 128 + 2) * b * b;
+  const size_t part_pan = (size_t)(jmax / 64 + 2) * b * b;
   size_t need = 0;
   need += 2 * round_up((size_t)jmax * 2 * b * 8, 256);   // WV[2] = [W | V]
   need += 2 * round_up((size_t)jmax * b * 8, 256);       // Wt[2] = V T
@@ -659,7 +664,7 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
   if (rc) return rc;
   const int npan = (n + b - 1) / b;
   const size_t part_cap = std::max<size_t>((size_t)8 * m * b, (size_t)256 * b * b);
-  const size_t part_pan = (size_t)(m / 128 + 2) * b * b;
+  const size_t part_pan = (size_t)(m / 64 + 2) * b * b;
   size_t need = 0;
   need += 2 * round_up((size_t)m * b * 8, 256);       // Vq, Wtq
   need += 2 * round_up((size_t)n * b * 8, 256);       // Up, Wtp
