@@ -300,8 +300,11 @@ static int syr2k(Ctx &cx, int prec, int j, int pb, const double *WV, int64_t ldw
 // three chunks (two drains for the panel's three such kernels: fewer chunks
 // leave them waiting longer, more add launch tails that cost more than they
 // save), each at least two full rounds of resident 128 x 128 workgroups.
-// Every element is still computed by one tile in the same order.
+// Every element is still computed by one tile in the same order.  The SYR2K
+// takes at most two (its upper tiles exit early, so CUs drain within a launch
+// too; measured on SY2SB n=16384: 158.8 ms with two, 160.1 with three).
 constexpr int kMaxChunks = 3;
+constexpr int kMaxSyr2kChunks = 2;
 // Below a trailing order (GE2GB: update rows) of 8192 the panel beside the
 // update is the longer of the two by a wider margin; there the update's
 // launches reserve 20 KB of extra LDS per workgroup, which leaves one of its
@@ -322,7 +325,7 @@ static int syr2k_chunked(Ctx &cx, int prec, int j, int pb, const double *WV, int
                          double *A2, int64_t lda, int c0, int c1, hipStream_t s) {
   if (c1 <= c0) return 0;
   const int64_t nI = (j - c0 + 127) / 128, nJ = (c1 - c0 + 127) / 128;
-  const int nck = update_chunks(cx.st, nJ * nI - nJ * (nJ - 1) / 2);
+  const int nck = std::min(kMaxSyr2kChunks, update_chunks(cx.st, nJ * nI - nJ * (nJ - 1) / 2));
   auto area = [&](double x) {  // lower-trapezoid elements of columns [c0, x)
     const double r0 = j - c0, r1 = j - x;
     return 0.5 * (r0 * (r0 + 1) - r1 * (r1 + 1));
