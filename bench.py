@@ -15,6 +15,7 @@ the FP64 matrix-core peak, and the CPU oracle timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
        [--no-forms] [--no-cpu-baseline] [--profile-only] [--roofline-only]
+       [--serial-only]
 """
 from __future__ import annotations
 
@@ -120,7 +121,8 @@ def time_steps(run, restore, steps, stream):
 
 def cpu_baseline(p, A_dev):
     """The oracle as it stands, on the first k reflector columns (steps) of
-    the same matrix (a bounded sample), rated with the same flop model."""
+    the same matrix (a bounded sample), rated with the same flop model; timed
+    on all host threads and again on one thread (a shorter sample)."""
     import numpy as np
 
     import oracle
@@ -131,33 +133,49 @@ def cpu_baseline(p, A_dev):
     m = p["m"] if is_ge else n
     A = A_dev.cpu().numpy()
     run = (lambda k: orc.ge2gb(A, w, ncols=k)) if is_ge else (lambda k: orc.sy2sb(A, w, ncols=k))
-    # per-column cost from two short runs (the oracle's full-matrix copy in
-    # and out is a fixed cost), then a sample of about 20 s
-    t0 = time.perf_counter()
-    run(2)
-    t2 = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    run(10)
-    t10 = time.perf_counter() - t0
-    per_col = max((t10 - t2) / 8.0, 1e-4)
-    fixed = max(t2 - 2.0 * per_col, 0.0)
-    ncol = n if is_ge else n - w - 1
-    k = int(max(10, min(ncol, (20.0 - fixed) / per_col)))
-    t0 = time.perf_counter()
-    run(k)
-    dt = time.perf_counter() - t0
+
+    def flops_of(k):
+        if is_ge:
+            # step c: left reflector on an (m-c) x (n-c) block, right one on an
+            # (m-c-1) x (n-c-w) block, 4 flops per entry each
+            return sum(4.0 * (m - c) * (n - c) + 4.0 * (m - c - 1) * max(n - c - w, 0)
+                       for c in range(k))
+        return sum(4.0 * (n - c - w) ** 2 for c in range(k))
+
+    def sample(budget_s):
+        # per-column cost from two short runs (the oracle's full-matrix copy in
+        # and out is a fixed cost), then a sample of about budget_s seconds
+        t0 = time.perf_counter()
+        run(2)
+        t2 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        run(10)
+        t10 = time.perf_counter() - t0
+        per_col = max((t10 - t2) / 8.0, 1e-4)
+        fixed = max(t2 - 2.0 * per_col, 0.0)
+        ncol = n if is_ge else n - w - 1
+        k = int(max(10, min(ncol, (budget_s - fixed) / per_col)))
+        t0 = time.perf_counter()
+        run(k)
+        dt = time.perf_counter() - t0
+        return k, dt, flops_of(k) / dt / 1e9
+
+    threads = orc.threads()
+    k, dt, rate = sample(20.0)
+    orc.set_threads(1)
+    try:
+        k1, dt1, rate1 = sample(8.0)
+    finally:
+        orc.set_threads(threads)
     if is_ge:
-        # step c: left reflector on an (m-c) x (n-c) block, right one on an
-        # (m-c-1) x (n-c-w) block, 4 flops per entry each
-        flops = sum(4.0 * (m - c) * (n - c) + 4.0 * (m - c - 1) * max(n - c - w, 0)
-                    for c in range(k))
         what = f"first {k} of {n} steps of the {m} x {n}, w={w} matrix"
     else:
-        flops = sum(4.0 * (n - c - w) ** 2 for c in range(k))
         what = (f"first {k} of {n - w - 1} reflector columns of the n={n}, w={w} matrix "
                 f"(4 j^2 flops per column of trailing order j)")
-    return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": orc.threads(), "kind": "oracle",
-            "sample": f"{what}, {dt:.1f} s incl. the oracle's full-matrix copy in and out"}
+    return {"value": rate, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"{what}, {dt:.1f} s incl. the oracle's full-matrix copy in and out",
+            "single_thread": {"value": rate1, "unit": "GFLOP/s", "cores": 1,
+                              "sample": f"first {k1} columns/steps, {dt1:.1f} s"}}
 
 
 def batch_bytes(ns, w, b):
@@ -362,6 +380,9 @@ def main():
                     help="warm up and run the steps only (for rocprofv3)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="one serial warm-up and the serial per-kernel step only (for rocprofv3)")
+    ap.add_argument("--serial-only", action="store_true",
+                    help="a plain device copy of the matrix (calibrates rocprofv3's FETCH_SIZE "
+                         "and WRITE_SIZE counters) and one serial reduction (for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only; this build has no multi-GPU path "
@@ -405,6 +426,20 @@ def main():
         return run
 
     run_eager = runner("fp64")
+    if args.serial_only:
+        # calibration: one copy that reads and writes exactly the matrix bytes
+        B = torch.empty_like(A0)
+        torch.cuda.synchronize()
+        B.copy_(A0)
+        torch.cuda.synchronize()
+        del B
+        restore()
+        torch.cuda.synchronize()
+        serial_call(br, A, is_ge, w, b)
+        torch.cuda.synchronize()
+        print(json.dumps({"metric": METRIC, "workload": args.workload, "serial_only": True,
+                          "copy_bytes": 2 * A0.numel() * 8}))
+        return
     if args.roofline_only:
         # the serial per-kernel step alone, after one serial warm-up: under
         # rocprofv3 every launch of the trace is one the roofline figure covers

@@ -109,7 +109,10 @@ BANDRED_API int bandred_ge2gb(int64_t m, int64_t n, int64_t w, int64_t b, double
  * or a larger size has reserved the workspace; under capture it allocates
  * nothing and returns BANDRED_ERR_UNSUPPORTED otherwise (or while profiling
  * is enabled).  Replays share the device's workspace with every other call:
- * the caller keeps them from overlapping.
+ * the caller keeps them from overlapping.  A workspace that a captured graph
+ * refers to is never freed: when a later eager call needs a larger one, the
+ * old one is kept (until the process ends) so that the graph stays valid.
+ * Runtime failures are reported by bandred_status.
  * Extra arguments: prec (arg 7), opts (arg 8, may be NULL), stream (arg 9). */
 BANDRED_API int bandred_sy2sb_ex(int64_t n, int64_t w, int64_t b, double *A, int64_t lda,
                      double *tau, int prec, const bandred_opts_t *opts,
@@ -133,13 +136,43 @@ BANDRED_API int bandred_ge2gb_ex(int64_t m, int64_t n, int64_t w, int64_t b, dou
  *          may be NULL for matrices with n[i] <= w)                   (arg 7)
  *   prec   BANDRED_FP64 or BANDRED_FP32_UPDATE                       (arg 8)
  *   stream hipStream_t or NULL                                       (arg 9)
- * Asynchronous like the _ex calls. */
+ * Asynchronous like the _ex calls.  The matrix table is uploaded to the
+ * device once per distinct content; a call may be captured into a HIP graph
+ * after an eager call with the same table.  A table (and the kernel's
+ * scratch) that a captured graph refers to is never rewritten or freed by
+ * later calls. */
 BANDRED_API int bandred_sy2sb_batched(int64_t count, const int64_t *n, int64_t w, int64_t b,
                           double *const *A, const int64_t *lda,
                           double *const *tau, int prec, void *stream);
 
 /* Static description of a status code. */
 BANDRED_API const char *bandred_status_string(int status);
+
+/* Runtime status of the asynchronous calls (the _ex and _batched entry
+ * points report argument errors at once but run on the device afterwards).
+ * Waits for all work on `stream` (hipStream_t, NULL = null stream), then
+ * returns the device status word of the most recent call on the current
+ * device: 0, or BANDRED_ERR_TIMEOUT when a bounded inter-workgroup wait of a
+ * panel factorisation gave up.  In that case the panel kernels of the call
+ * exit at their next wait and every later product of the call returns at
+ * once, so the outputs are invalid (not partially updated in a defined way).
+ * Each call clears the word when it starts: query it after the call whose
+ * status is wanted and before the next one on the same device.  Must not be
+ * called while `stream` is being captured into a HIP graph. */
+BANDRED_API int bandred_status(void *stream);
+
+/* Frees the library's device memory on the current device (workspace,
+ * batched tables and scratch, including those kept for captured graphs) after
+ * waiting for the device to be idle.  Every HIP graph that captured a call of
+ * this library on the device becomes invalid and must not be replayed again.
+ * Later calls allocate afresh. */
+BANDRED_API int bandred_release(void);
+
+/* Bound of one inter-workgroup wait inside the panel kernels, in
+ * microseconds, for later calls on the current device (default 10 s; us <= 0
+ * restores the default).  A wait that exceeds it makes the call report
+ * BANDRED_ERR_TIMEOUT.  Meant for tests of that error path. */
+BANDRED_API int bandred_set_wait_limit_us(double us);
 
 /* Per-kernel-class device time of the most recent call (diagnostics).
  * When enabled (on != 0) every launch is bracketed by HIP events on the

@@ -58,6 +58,8 @@ class Oracle:
         lib.oracle_house.restype = ctypes.c_double
         lib.oracle_threads.argtypes = []
         lib.oracle_threads.restype = ctypes.c_int
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = None
         self.lib = lib
         self.path = path
 
@@ -67,6 +69,9 @@ class Oracle:
 
     def threads(self) -> int:
         return int(self.lib.oracle_threads())
+
+    def set_threads(self, nthreads: int) -> None:
+        self.lib.oracle_set_threads(int(nthreads))
 
     def house(self, x):
         """Householder vector of ``x``: returns (v, tau, beta) with v[0] = 1."""

@@ -55,6 +55,14 @@ int oracle_threads(void) {
 #endif
 }
 
+void oracle_set_threads(int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+}
+
 /* Euclidean norm of x[0..L-1] (stride inc), scaled by max |x_i| so that the
  * squares neither overflow nor underflow. */
 static double norm2_scaled(int64_t L, const double *x, int64_t inc) {

@@ -48,6 +48,10 @@ double oracle_house(int64_t L, double *x, int64_t inc, double *beta);
 /* Number of OpenMP threads the oracle uses. */
 int oracle_threads(void);
 
+/* Set the number of OpenMP threads for later calls (results do not depend
+ * on it; used to time the oracle single-threaded). */
+void oracle_set_threads(int nthreads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,6 +67,9 @@ def load(path: str = LIB_PATH):
     lib.bandred_sy2sb_batched.argtypes = [_i64, ctypes.POINTER(_i64), _i64, _i64,
                                           ctypes.POINTER(_vp), ctypes.POINTER(_i64),
                                           ctypes.POINTER(_vp), ctypes.c_int, _vp]
+    lib.bandred_status.argtypes = [_vp]
+    lib.bandred_release.argtypes = []
+    lib.bandred_set_wait_limit_us.argtypes = [ctypes.c_double]
     lib.bandred_status_string.argtypes = [ctypes.c_int]
     lib.bandred_status_string.restype = ctypes.c_char_p
     lib.bandred_profile_enable.argtypes = [ctypes.c_int]
@@ -74,7 +77,8 @@ def load(path: str = LIB_PATH):
     lib.bandred_profile_name.argtypes = [ctypes.c_int]
     lib.bandred_profile_name.restype = ctypes.c_char_p
     for name in ("bandred_sy2sb", "bandred_ge2gb", "bandred_sy2sb_ex", "bandred_ge2gb_ex",
-                 "bandred_sy2sb_batched", "bandred_profile_enable", "bandred_profile_read"):
+                 "bandred_sy2sb_batched", "bandred_profile_enable", "bandred_profile_read",
+                 "bandred_status", "bandred_set_wait_limit_us", "bandred_release"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -122,6 +126,18 @@ def bandred_status_string(code: int) -> str:
     return status_string(code)
 
 
+def bandred_status(stream=None) -> int:
+    return load().bandred_status(stream)
+
+
+def bandred_release() -> int:
+    return load().bandred_release()
+
+
+def bandred_set_wait_limit_us(us: float) -> int:
+    return load().bandred_set_wait_limit_us(float(us))
+
+
 def bandred_profile_enable(on: bool) -> int:
     return load().bandred_profile_enable(1 if on else 0)
 
@@ -164,10 +180,23 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _check_status(fn: str, handle, check: bool):
+    """After an asynchronous call: unless the stream is being captured into
+    a graph (or check is False), wait for it and raise on a device-side
+    failure (a panel wait that timed out)."""
+    import torch
+
+    if not check or torch.cuda.is_current_stream_capturing():
+        return
+    _check(fn + " (device status)", bandred_status(handle))
+
+
 def sy2sb(A, w: int, b: int | None = None, prec="fp64", lookahead: bool = True,
-          panel_rows: int = 0, panel_method: int = 0, stream=None, tau=None):
+          panel_rows: int = 0, panel_method: int = 0, stream=None, tau=None, check: bool = True):
     """Reduce the symmetric column-major CUDA tensor ``A`` (lower triangle) to
-    band width ``w`` in place; returns tau (device tensor)."""
+    band width ``w`` in place; returns tau (device tensor).  With ``check``
+    (and outside graph capture) the call waits for the device and raises if
+    the reduction reported a runtime failure."""
     import torch
 
     n = A.shape[0]
@@ -177,13 +206,15 @@ def sy2sb(A, w: int, b: int | None = None, prec="fp64", lookahead: bool = True,
         tau = torch.zeros(max(n - w, 1), dtype=torch.float64, device=A.device)
     p = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
     o = Opts(1 if lookahead else 0, int(panel_rows), int(panel_method))
-    rc = bandred_sy2sb_ex(n, w, b, A.data_ptr(), lda, tau.data_ptr(), p, o, _stream_handle(stream))
+    h = _stream_handle(stream)
+    rc = bandred_sy2sb_ex(n, w, b, A.data_ptr(), lda, tau.data_ptr(), p, o, h)
     _check("bandred_sy2sb_ex", rc)
+    _check_status("bandred_sy2sb_ex", h, check)
     return tau[: max(n - w, 0)]
 
 
 def ge2gb(A, w: int, b: int | None = None, prec="fp64", lookahead: bool = True,
-          panel_rows: int = 0, panel_method: int = 0, stream=None):
+          panel_rows: int = 0, panel_method: int = 0, stream=None, check: bool = True):
     """Reduce the column-major CUDA tensor ``A`` (m >= n) to upper
     triangular-band width ``w`` in place; returns (tauq, taup)."""
     import torch
@@ -195,13 +226,15 @@ def ge2gb(A, w: int, b: int | None = None, prec="fp64", lookahead: bool = True,
     taup = torch.zeros(max(n, 1), dtype=torch.float64, device=A.device)
     p = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
     o = Opts(1 if lookahead else 0, int(panel_rows), int(panel_method))
-    rc = bandred_ge2gb_ex(m, n, w, b, A.data_ptr(), lda, tauq.data_ptr(), taup.data_ptr(), p, o,
-                          _stream_handle(stream))
+    h = _stream_handle(stream)
+    rc = bandred_ge2gb_ex(m, n, w, b, A.data_ptr(), lda, tauq.data_ptr(), taup.data_ptr(), p, o, h)
     _check("bandred_ge2gb_ex", rc)
+    _check_status("bandred_ge2gb_ex", h, check)
     return tauq[:n], taup[:n]
 
 
-def sy2sb_batched(mats, w: int, b: int | None = None, prec="fp64", stream=None):
+def sy2sb_batched(mats, w: int, b: int | None = None, prec="fp64", stream=None,
+                  check: bool = True):
     """Reduce a list of symmetric column-major CUDA tensors in one call;
     returns the list of tau tensors."""
     import torch
@@ -216,7 +249,8 @@ def sy2sb_batched(mats, w: int, b: int | None = None, prec="fp64", stream=None):
         t = torch.zeros(max(n - w, 1), dtype=torch.float64, device=A.device)
         taus.append(t)
     p = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
-    rc = bandred_sy2sb_batched(len(mats), ns, w, b, ptrs, lds, [t.data_ptr() for t in taus], p,
-                               _stream_handle(stream))
+    h = _stream_handle(stream)
+    rc = bandred_sy2sb_batched(len(mats), ns, w, b, ptrs, lds, [t.data_ptr() for t in taus], p, h)
     _check("bandred_sy2sb_batched", rc)
+    _check_status("bandred_sy2sb_batched", h, check)
     return [t[: max(n - w, 0)] for t, n in zip(taus, ns)]

@@ -87,44 +87,75 @@ struct ProfScope {
 // ---------------------------------------------------------------------------
 // workspace
 // ---------------------------------------------------------------------------
+
+// A device table of one batched call's matrices.  A table that a captured
+// HIP graph has used is never rewritten or freed (the graph keeps its device
+// address); other tables are reused for later uploads.
+struct BatchTable {
+  std::vector<BatchEntry> host;  // content (sorted as uploaded)
+  BatchEntry *dev = nullptr;
+  size_t cap = 0;                // entries dev holds
+  bool captured = false;
+};
+
 struct DevState {
-  bool init = false;
+  bool props = false;         // device properties read (no allocation)
+  bool init = false;          // streams, events and the status words created
+  int num_cu = 0;
+  long long timeout_ticks = 0;
+  long long default_ticks = 0;
   char *base = nullptr;
   size_t bytes = 0;
+  bool base_captured = false; // a captured graph refers to base
+  std::vector<void *> retired;// workspaces a captured graph may still use
   hipEvent_t done = nullptr;  // completion of the previous call's work
   hipStream_t aux = nullptr;  // look-ahead (panel) stream
   hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr, ev_d = nullptr;
   int *flags = nullptr;       // [0] status, [1] abort   (device)
-  long long timeout_ticks = 0;
-  int num_cu = 0;
-  // batched calls: pinned copy of the last uploaded matrix table, its device
-  // copy, the work counter and the per-workgroup scratch
-  BatchEntry *bt_host = nullptr;
-  BatchEntry *bt_dev = nullptr;
-  size_t bt_cap = 0;          // entries of bt_host / bt_dev
-  int64_t bt_count = -1;      // entries of the last upload
-  hipEvent_t bt_ev = nullptr; // completion of the last table upload
+  // batched calls: uploaded matrix tables, a pinned staging copy, the work
+  // counter and the per-workgroup scratch
+  std::vector<BatchTable> tables;
+  BatchEntry *bt_stage = nullptr;
+  size_t bt_stage_cap = 0;
+  hipEvent_t bt_ev = nullptr; // completion of the last upload from the staging copy
   unsigned *bt_queue = nullptr;
   double *bt_ws = nullptr;
   int bt_wgs = 0;             // workgroups bt_ws holds
+  bool bt_ws_captured = false;
 };
 static std::mutex g_mu;
 static DevState g_dev[64];
 
+// Device properties only: no stream, event or memory is created.
+static int dev_props(DevState &st, int dev) {
+  if (st.props) return 0;
+  hipDeviceProp_t prop;
+  BR_HIP_CHECK(hipGetDeviceProperties(&prop, dev));
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return BANDRED_ERR_UNSUPPORTED;
+  st.num_cu = prop.multiProcessorCount;
+  int rate_khz = 0;
+  BR_HIP_CHECK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
+  if (rate_khz <= 0) rate_khz = 100000;
+  st.default_ticks = (long long)rate_khz * 1000LL * 10LL;  // 10 s per wait
+  if (st.timeout_ticks <= 0) st.timeout_ticks = st.default_ticks;
+  st.props = true;
+  return 0;
+}
+
+static int current_device(int *dev) {
+  BR_HIP_CHECK(hipGetDevice(dev));
+  if (*dev < 0 || *dev >= 64) return BANDRED_ERR_UNSUPPORTED;
+  return 0;
+}
+
 static int dev_state(DevState **out) {
   int dev = 0;
-  BR_HIP_CHECK(hipGetDevice(&dev));
-  if (dev < 0 || dev >= 64) return BANDRED_ERR_UNSUPPORTED;
+  int rc = current_device(&dev);
+  if (rc) return rc;
   DevState &st = g_dev[dev];
+  rc = dev_props(st, dev);
+  if (rc) return rc;
   if (!st.init) {
-    hipDeviceProp_t prop;
-    BR_HIP_CHECK(hipGetDeviceProperties(&prop, dev));
-    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return BANDRED_ERR_UNSUPPORTED;
-    st.num_cu = prop.multiProcessorCount;
-    int rate_khz = 0;
-    BR_HIP_CHECK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
-    if (rate_khz <= 0) rate_khz = 100000;
-    st.timeout_ticks = (long long)rate_khz * 1000LL * 10LL;  // 10 s per wait
     BR_HIP_CHECK(hipEventCreateWithFlags(&st.done, hipEventDisableTiming));
     BR_HIP_CHECK(hipEventCreateWithFlags(&st.ev_a, hipEventDisableTiming));
     BR_HIP_CHECK(hipEventCreateWithFlags(&st.ev_b, hipEventDisableTiming));
@@ -137,6 +168,7 @@ static int dev_state(DevState **out) {
     BR_HIP_CHECK(hipEventCreateWithFlags(&st.bt_ev, hipEventDisableTiming));
     BR_HIP_CHECK(hipEventRecord(st.bt_ev, st.aux));
     BR_HIP_CHECK(hipMalloc((void **)&st.bt_queue, 256));
+    BR_HIP_CHECK(hipDeviceSynchronize());
     st.init = true;
   }
   *out = &st;
@@ -144,12 +176,18 @@ static int dev_state(DevState **out) {
 }
 
 // Grow the workspace to at least `bytes`; waits for the previous call first.
+// A workspace that a captured HIP graph refers to is retired, not freed: a
+// replay of that graph after this call still finds its memory.
 static int ws_reserve(DevState &st, size_t bytes) {
   if (bytes <= st.bytes) return 0;
   BR_HIP_CHECK(hipEventSynchronize(st.done));
-  if (st.base) BR_HIP_CHECK(hipFree(st.base));
+  if (st.base) {
+    if (st.base_captured) st.retired.push_back(st.base);
+    else BR_HIP_CHECK(hipFree(st.base));
+  }
   st.base = nullptr;
   st.bytes = 0;
+  st.base_captured = false;
   const size_t want = bytes + (bytes >> 3);
   if (hipMalloc((void **)&st.base, want) != hipSuccess) {
     (void)hipGetLastError();
@@ -164,12 +202,14 @@ static int ws_reserve(DevState &st, size_t bytes) {
 // (the workspace must already be reserved by an earlier eager call at least
 // as large), skips the wait on and the record of the cross-call completion
 // event (the caller orders replays against other calls), and runs without
-// the profiling events.
-static int capture_check(hipStream_t s, size_t need, const DevState &st, bool *capturing) {
+// the profiling events.  The workspace is then marked as referenced by a
+// graph (see ws_reserve).
+static int capture_check(hipStream_t s, size_t need, DevState &st, bool *capturing) {
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   BR_HIP_CHECK(hipStreamIsCapturing(s, &cap));
   *capturing = cap != hipStreamCaptureStatusNone;
   if (*capturing && (g_prof || need > st.bytes)) return BANDRED_ERR_UNSUPPORTED;
+  if (*capturing) st.base_captured = true;
   return 0;
 }
 
@@ -216,6 +256,7 @@ static int gemm(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int 
   d.gate = gate; d.gate_val = gate_val;
   d.C2 = C2; d.ldc2 = ldc2; d.c2_trans = c2_trans;
   d.lds_pad = lds_pad;
+  d.abort = cx.st->flags + 1;
   d.prio = (cls == C_PANEL || cls == C_GEMM_SMALL) ? 1 : 0;
   const int bm = (M <= 64 && N <= 64) ? 64 : 128;
   const int tiles = ((M + bm - 1) / bm) * ((N + bm - 1) / bm);
@@ -266,7 +307,8 @@ static int gemm(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int 
     if (rc) return rc;
   }
   ProfScope ps(C_REDUCE, 0.0, s);
-  return launch_reduce_partials(cx.part, ks, M, N, alpha, C, ldc, beta, s, gate, gate_val);
+  return launch_reduce_partials(cx.part, ks, M, N, alpha, C, ldc, beta, s, gate, gate_val,
+                                cx.st->flags + 1);
 }
 
 // A2(lower, columns [c0, c1)) -= W V^T + V W^T with WV = [W | V] (j x 2pb).
@@ -275,6 +317,7 @@ static int syr2k(Ctx &cx, int prec, int j, int pb, const double *WV, int64_t ldw
   if (c1 <= c0) return 0;
   GemmDesc d{};
   d.lds_pad = lds_pad;
+  d.abort = cx.st->flags + 1;
   d.M = j; d.N = j; d.K = 2 * pb;
   d.A = WV; d.lda = ldwv; d.B = WV; d.ldb = ldwv;
   d.C = A2; d.ldc = lda;
@@ -508,19 +551,22 @@ static int panel_factor(Ctx &cx, bool rowmajor, double *P, int64_t ldp, int m, i
 // ---------------------------------------------------------------------------
 // SY2SB
 // ---------------------------------------------------------------------------
+// na: the no-allocation state (static scratch, one stream, no events), or
+// nullptr for the library's own workspace.
 static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t lda, double *tau,
-                      int prec, const bandred_opts_t *opts, hipStream_t s) {
+                      int prec, const bandred_opts_t *opts, hipStream_t s,
+                      DevState *na = nullptr) {
   if (n64 <= w64 + 1) {
     if (n64 > w64) return launch_fill(tau, n64 - w64, 0.0, s);  // one trivial reflector
     return 0;
   }
   if (n64 > (int64_t)1 << 30) return BANDRED_ERR_UNSUPPORTED;
   const int n = (int)n64, w = (int)w64, b = (int)b64;
-  const int lookahead = opts ? opts->lookahead : 1;
+  const int lookahead = na ? 0 : (opts ? opts->lookahead : 1);
   const int panel_rows = opts ? opts->panel_rows : 0;
   const int method = opts ? opts->panel_method : 0;
-  DevState *st = nullptr;
-  int rc = dev_state(&st);
+  DevState *st = na;
+  int rc = na ? 0 : dev_state(&st);
   if (rc) return rc;
 
   const int nref = n - w - 1;  // reflector columns 0 .. n-w-2
@@ -539,10 +585,18 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
   need += 8192;
   std::lock_guard<std::mutex> lk(g_mu);
   bool capturing = false;
-  rc = capture_check(s, need, *st, &capturing);
-  if (rc) return rc;
-  rc = ws_reserve(*st, need);
-  if (rc) return rc;
+  if (na) {
+    if (need > na->bytes || g_prof) return BANDRED_ERR_UNSUPPORTED;
+  } else {
+    rc = capture_check(s, need, *st, &capturing);
+    if (rc) return rc;
+    rc = ws_reserve(*st, need);
+    if (rc) return rc;
+  }
+  // calls through the library's workspace are ordered on it by the
+  // completion event of the previous call (not under capture, where the
+  // caller orders replays, and not on the no-allocation path)
+  const bool ordered = !capturing && !na;
   Arena ar(st->base);
   double *WVbuf[2] = {ar.take<double>((size_t)jmax * 2 * b), ar.take<double>((size_t)jmax * 2 * b)};
   double *Wtb[2] = {ar.take<double>((size_t)jmax * b), ar.take<double>((size_t)jmax * b)};
@@ -561,7 +615,7 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
   hipStream_t ps = lookahead ? st->aux : s;  // panel stream
   Ctx cxp{st, ps, partp, part_pan};
 
-  if (!capturing) BR_HIP_CHECK(hipStreamWaitEvent(s, st->done, 0));
+  if (ordered) BR_HIP_CHECK(hipStreamWaitEvent(s, st->done, 0));
   rc = launch_fill_u32(counters, npan + 1, 0u, s); if (rc) return rc;
   rc = launch_fill_u32((unsigned *)pflags, 2 * (npan + 1), 0u, s); if (rc) return rc;
   rc = launch_fill_u32((unsigned *)pstruct, (int64_t)(npan + 1) * 2 * kNbMax, 0u, s);
@@ -645,7 +699,7 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
       BR_HIP_CHECK(hipStreamWaitEvent(s, st->ev_b, 0));
     }
   }
-  if (!capturing) BR_HIP_CHECK(hipEventRecord(st->done, s));
+  if (ordered) BR_HIP_CHECK(hipEventRecord(st->done, s));
   return 0;
 }
 
@@ -858,14 +912,23 @@ static int batched_impl(int64_t count, const int64_t *n, int w, int b, double *c
     std::lock_guard<std::mutex> lk(g_mu);
     const int nwg = (int)std::min<int64_t>((int64_t)tab.size(), st->num_cu);
     const size_t tb = tab.size() * sizeof(BatchEntry);
-    const bool same = st->bt_count == (int64_t)tab.size() && memcmp(st->bt_host, tab.data(), tb) == 0;
-    if (capturing && (!same || nwg > st->bt_wgs)) return BANDRED_ERR_UNSUPPORTED;
+    auto same_as = [&](const BatchTable &t) {
+      return t.host.size() == tab.size() && memcmp(t.host.data(), tab.data(), tb) == 0;
+    };
+    BatchTable *table = nullptr;
+    for (BatchTable &t : st->tables)
+      if (same_as(t)) table = &t;
+    if (capturing && (g_prof || !table || nwg > st->bt_wgs)) return BANDRED_ERR_UNSUPPORTED;
     if (!capturing) BR_HIP_CHECK(hipStreamWaitEvent(s, st->done, 0));
     if (nwg > st->bt_wgs) {
       BR_HIP_CHECK(hipEventSynchronize(st->done));
-      if (st->bt_ws) BR_HIP_CHECK(hipFree(st->bt_ws));
+      if (st->bt_ws) {
+        if (st->bt_ws_captured) st->retired.push_back(st->bt_ws);
+        else BR_HIP_CHECK(hipFree(st->bt_ws));
+      }
       st->bt_ws = nullptr;
       st->bt_wgs = 0;
+      st->bt_ws_captured = false;
       if (hipMalloc((void **)&st->bt_ws, (size_t)nwg * batched_ws_doubles() * sizeof(double)) !=
           hipSuccess) {
         (void)hipGetLastError();
@@ -874,29 +937,44 @@ static int batched_impl(int64_t count, const int64_t *n, int w, int b, double *c
       }
       st->bt_wgs = nwg;
     }
-    if (!same) {
-      BR_HIP_CHECK(hipEventSynchronize(st->bt_ev));  // the pinned copy is free again
-      if (tab.size() > st->bt_cap) {
-        BR_HIP_CHECK(hipEventSynchronize(st->done));  // no kernel reads the old table
-        if (st->bt_host) BR_HIP_CHECK(hipHostFree(st->bt_host));
-        if (st->bt_dev) BR_HIP_CHECK(hipFree(st->bt_dev));
-        st->bt_host = nullptr;
-        st->bt_dev = nullptr;
-        st->bt_cap = 0;
-        st->bt_count = -1;
+    if (!table) {
+      // reuse a table no captured graph refers to (the largest one that fits),
+      // or add a new one; then upload through the pinned staging copy
+      BR_HIP_CHECK(hipEventSynchronize(st->bt_ev));  // the staging copy is free again
+      for (BatchTable &t : st->tables)
+        if (!t.captured && t.cap >= tab.size() && (!table || t.cap > table->cap)) table = &t;
+      if (table) {
+        BR_HIP_CHECK(hipEventSynchronize(st->done));  // no kernel reads its old content
+      } else {
+        st->tables.emplace_back();
+        table = &st->tables.back();
+        table->cap = tab.size() + tab.size() / 4 + 64;
+        if (hipMalloc((void **)&table->dev, table->cap * sizeof(BatchEntry)) != hipSuccess) {
+          (void)hipGetLastError();
+          st->tables.pop_back();
+          return BANDRED_ERR_ALLOC;
+        }
+      }
+      if (tab.size() > st->bt_stage_cap) {
+        if (st->bt_stage) BR_HIP_CHECK(hipHostFree(st->bt_stage));
+        st->bt_stage = nullptr;
+        st->bt_stage_cap = 0;
         const size_t cap_e = tab.size() + tab.size() / 4 + 64;
-        if (hipHostMalloc((void **)&st->bt_host, cap_e * sizeof(BatchEntry), hipHostMallocDefault) !=
-                hipSuccess ||
-            hipMalloc((void **)&st->bt_dev, cap_e * sizeof(BatchEntry)) != hipSuccess) {
+        if (hipHostMalloc((void **)&st->bt_stage, cap_e * sizeof(BatchEntry),
+                          hipHostMallocDefault) != hipSuccess) {
           (void)hipGetLastError();
           return BANDRED_ERR_ALLOC;
         }
-        st->bt_cap = cap_e;
+        st->bt_stage_cap = cap_e;
       }
-      memcpy(st->bt_host, tab.data(), tb);
-      BR_HIP_CHECK(hipMemcpyAsync(st->bt_dev, st->bt_host, tb, hipMemcpyHostToDevice, s));
+      table->host = tab;
+      memcpy(st->bt_stage, tab.data(), tb);
+      BR_HIP_CHECK(hipMemcpyAsync(table->dev, st->bt_stage, tb, hipMemcpyHostToDevice, s));
       BR_HIP_CHECK(hipEventRecord(st->bt_ev, s));
-      st->bt_count = (int64_t)tab.size();
+    }
+    if (capturing) {
+      table->captured = true;
+      st->bt_ws_captured = true;
     }
     rc = launch_fill_u32(st->bt_queue, 1, 0u, s);
     if (rc) return rc;
@@ -904,7 +982,7 @@ static int batched_impl(int64_t count, const int64_t *n, int w, int b, double *c
     for (const BatchEntry &e : tab) flops += 4.0 / 3.0 * (double)e.n * e.n * e.n;
     {
       ProfScope ps(C_BATCHED, flops, s);
-      rc = launch_batched(prec, st->bt_dev, (int)tab.size(), w, b, st->bt_queue, st->bt_ws, nwg, s);
+      rc = launch_batched(prec, table->dev, (int)tab.size(), w, b, st->bt_queue, st->bt_ws, nwg, s);
     }
     if (rc) return rc;
     if (!capturing) BR_HIP_CHECK(hipEventRecord(st->done, s));
@@ -917,13 +995,15 @@ static int batched_impl(int64_t count, const int64_t *n, int w, int b, double *c
   return 0;
 }
 
+// Device status word of the most recent call on the current device (0, or
+// BANDRED_ERR_TIMEOUT), after the work on stream s has finished.
 static int read_status(hipStream_t s) {
   DevState *st = nullptr;
   int rc = dev_state(&st);
   if (rc) return rc;
-  int flags[2] = {0, 0};
-  BR_HIP_CHECK(hipMemcpyAsync(flags, st->flags, sizeof(flags), hipMemcpyDeviceToHost, s));
   BR_HIP_CHECK(hipStreamSynchronize(s));
+  int flags[2] = {0, 0};
+  BR_HIP_CHECK(hipMemcpy(flags, st->flags, sizeof(flags), hipMemcpyDeviceToHost));
   return flags[0];
 }
 
@@ -1044,6 +1124,57 @@ const char *bandred_status_string(int status) {
   }
   if (status < 0) return "invalid argument";
   return "unknown status";
+}
+
+int bandred_status(void *stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return read_status((hipStream_t)stream);
+}
+
+int bandred_release(void) {
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevState &st = g_dev[dev];
+  if (!st.init) return 0;
+  BR_HIP_CHECK(hipDeviceSynchronize());
+  for (void *p : st.retired) BR_HIP_CHECK(hipFree(p));
+  st.retired.clear();
+  if (st.base) BR_HIP_CHECK(hipFree(st.base));
+  st.base = nullptr;
+  st.bytes = 0;
+  st.base_captured = false;
+  for (BatchTable &t : st.tables)
+    if (t.dev) BR_HIP_CHECK(hipFree(t.dev));
+  st.tables.clear();
+  if (st.bt_stage) BR_HIP_CHECK(hipHostFree(st.bt_stage));
+  st.bt_stage = nullptr;
+  st.bt_stage_cap = 0;
+  if (st.bt_ws) BR_HIP_CHECK(hipFree(st.bt_ws));
+  st.bt_ws = nullptr;
+  st.bt_wgs = 0;
+  st.bt_ws_captured = false;
+  return 0;
+}
+
+int bandred_set_wait_limit_us(double us) {
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevState &st = g_dev[dev];
+  rc = dev_props(st, dev);
+  if (rc) return rc;
+  // the wall clock runs at default_ticks / 10 s
+  long long t = st.default_ticks;
+  if (us > 0.0) {
+    const double per_us = (double)st.default_ticks / 1e7;
+    t = (long long)(us * per_us);
+    if (t < 1) t = 1;
+  }
+  st.timeout_ticks = t;
+  return 0;
 }
 
 int bandred_profile_enable(int on) {

@@ -54,6 +54,8 @@ struct GemmDesc {
   int c2_trans;    // ... at (row, col) (ld ldc2), or transposed at (col, row)
   int prio;        // nonzero: the waves run at raised issue priority (panel products)
   int lds_pad;     // extra LDS bytes reserved per workgroup (limits residency per CU)
+  const int *abort;// when set and nonzero at launch, the kernel returns at once (a
+                   // panel factorisation of the same call gave up a bounded wait)
 };
 
 // Wave issue priority of the panel kernels.  The panel of the next step runs
@@ -96,7 +98,8 @@ int launch_gemm(int opa, int opb, int epi, int prec, const GemmDesc &d, int kspl
                 hipStream_t s);
 int launch_reduce_partials(const double *part, int ksplit, int M, int N, double alpha,
                            double *C, int64_t ldc, double beta, hipStream_t s,
-                           const int *gate = nullptr, int gate_val = 0);
+                           const int *gate = nullptr, int gate_val = 0,
+                           const int *abort = nullptr);
 int launch_panel(bool rowmajor, const PanelDesc &d, int nwg, hipStream_t s);
 int launch_larft(const double *S, int ldS, const double *tau, int nb, double *T, int ldT,
                  hipStream_t s, const int *gate = nullptr, int gate_val = 0);

@@ -230,6 +230,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm(GemmDesc d) {
   __shared__ T Bs[2 * NP * SB];
 
   if (d.gate && *d.gate != d.gate_val) return;
+  if (d.abort && *d.abort != 0) return;
   if (d.prio) __builtin_amdgcn_s_setprio(kPrioPanel);
   int i0, j0, kbeg, kend;
   if (EPI == E_SYR2K) {
@@ -426,8 +427,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm(GemmDesc d) {
 
 __global__ void k_reduce_partials(const double *part, int ksplit, int M, int N, double alpha,
                                   double *C, int64_t ldc, double beta, const int *gate,
-                                  int gate_val) {
+                                  int gate_val, const int *abort) {
   if (gate && *gate != gate_val) return;
+  if (abort && *abort != 0) return;
   __builtin_amdgcn_s_setprio(kPrioPanel);  // split-k sums: on the panel chain or alone
   const int64_t total = (int64_t)M * N;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
@@ -522,13 +524,13 @@ int launch_gemm(int opa, int opb, int epi, int prec, const GemmDesc &d, int kspl
 
 int launch_reduce_partials(const double *part, int ksplit, int M, int N, double alpha,
                            double *C, int64_t ldc, double beta, hipStream_t s, const int *gate,
-                           int gate_val) {
+                           int gate_val, const int *abort) {
   const int64_t total = (int64_t)M * N;
   if (total <= 0) return 0;
   int blocks = (int)((total + 255) / 256);
   if (blocks > 2048) blocks = 2048;
   hipLaunchKernelGGL(k_reduce_partials, dim3(blocks), dim3(256), 0, s, part, ksplit, M, N, alpha,
-                     C, ldc, beta, gate, gate_val);
+                     C, ldc, beta, gate, gate_val, abort);
   BR_HIP_CHECK(hipGetLastError());
   return 0;
 }

@@ -46,3 +46,24 @@ def ge_compare(Ag, tqg, tpg, Ao, tqo, tpo, w, nsteps=None):
     f = lambda msk: float(np.max(np.abs(Ag[msk] - Ao[msk]))) if msk.any() else 0.0
     return (f(band), f(left), f(right), float(np.max(np.abs(tqg[:ns] - tqo[:ns]), initial=0.0)),
             float(np.max(np.abs(tpg[:ns] - tpo[:ns]), initial=0.0)))
+
+
+def sy_band_max(Ao: np.ndarray, w: int, ncols: int | None = None) -> float:
+    """Largest |entry| of the symmetric band (0 <= i-j <= w) of a reduced
+    matrix: the scale of the band-entry tolerance (each entry of a backward
+    stable reduction is accurate to about u n times the largest one)."""
+    n = Ao.shape[0]
+    nc = n if ncols is None else ncols
+    i = np.arange(n)[:, None]
+    j = np.arange(nc)[None, :]
+    band = (i - j >= 0) & (i - j <= w)
+    return float(np.abs(Ao[:, :nc][band]).max())
+
+
+def ge_band_max(Ao: np.ndarray, w: int, lower: int = 0) -> float:
+    """Largest |entry| of the band -lower <= j-i <= w of a reduced matrix."""
+    m, n = Ao.shape
+    i = np.arange(m)[:, None]
+    j = np.arange(n)[None, :]
+    band = (j - i >= -lower) & (j - i <= w)
+    return float(np.abs(Ao[band]).max())

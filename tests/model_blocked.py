@@ -108,3 +108,111 @@ def ge2gb_blocked(A, w, b):
             D -= ((D @ U) @ Tp) @ U.T
         c += b
     return A, tauq, taup
+
+
+# ---------------------------------------------------------------------------
+# CholeskyQR2 + Householder reconstruction (the default panel method of the
+# GPU drivers), with the drivers' acceptance thresholds
+# ---------------------------------------------------------------------------
+
+CHOL1_REL = 1e-10  # first Cholesky: pivot > CHOL1_REL * original diagonal
+CHOL2_REL = 1e-6   # second Cholesky: the same test
+
+
+def _chol_checked(G, rel):
+    """Upper Cholesky factor of G, right-looking, and whether every pivot
+    (the Schur-complement diagonal) exceeded rel times the original diagonal.
+    A failing pivot is replaced by 1 and the factorisation continues, as in
+    the kernel."""
+    G = np.array(G, dtype=np.float64, copy=True)
+    b = G.shape[0]
+    d0 = np.diag(G).copy()
+    R = np.zeros_like(G)
+    ok = True
+    worst = np.inf
+    for k in range(b):
+        d = G[k, k]
+        worst = min(worst, d / d0[k] if d0[k] > 0 else 0.0)
+        ok = ok and d > rel * d0[k]
+        if d <= 0.0:
+            d = 1.0
+        r = np.sqrt(d)
+        R[k, k] = r
+        R[k, k + 1:] = G[k, k + 1:] / r
+        G[k + 1:, k + 1:] -= np.outer(R[k, k + 1:], R[k, k + 1:])
+    return R, ok, worst
+
+
+def cholqr2_recon(P):
+    """Factor the m x b panel P (m > b) as the drivers do by default.
+
+    Returns a dict with ``branch`` ("cholqr2" when both Cholesky factorisations
+    pass their pivot tests, else "fallback-chol1" / "fallback-chol2": the
+    drivers then factor the panel column by column), the smallest pivot
+    ratios, and for the accepted branch V (explicit, unit lower trapezoidal),
+    tau and beta (the diagonal of the Householder R).
+    Reconstruction (Ballard et al.): LU without pivoting of Q(0:b,:) - S with
+    S_k = -sign of the current pivot gives V = [L; Q(b:m,:) U^-1],
+    T = -U S L^-T, R_householder = S R."""
+    m, b = P.shape
+    R1, ok1, w1 = _chol_checked(P.T @ P, CHOL1_REL)
+    out = {"pivot_ratio1": w1}
+    if not ok1:
+        out["branch"] = "fallback-chol1"
+        return out
+    Q1 = np.linalg.solve(R1.T, P.T).T
+    R2, ok2, w2 = _chol_checked(Q1.T @ Q1, CHOL2_REL)
+    out["pivot_ratio2"] = w2
+    if not ok2:
+        out["branch"] = "fallback-chol2"
+        return out
+    Q = np.linalg.solve(R2.T, Q1.T).T
+    R = R2 @ R1
+    W = Q[:b, :].copy()
+    L = np.eye(b)
+    U = np.zeros((b, b))
+    S = np.zeros(b)
+    for k in range(b):
+        S[k] = -1.0 if W[k, k] >= 0.0 else 1.0
+        W[k, k] -= S[k]
+        U[k, k:] = W[k, k:]
+        L[k + 1:, k] = W[k + 1:, k] / W[k, k]
+        W[k + 1:, k + 1:] -= np.outer(L[k + 1:, k], U[k, k + 1:])
+    V = np.vstack([L, np.linalg.solve(U.T, Q[b:, :].T).T])
+    T = -U @ np.diag(S) @ np.linalg.inv(L).T
+    out.update(branch="cholqr2", V=V, tau=np.diag(T).copy(), beta=S * np.diag(R))
+    return out
+
+
+def conditioned_panel(m, b, kappa, kind, seed):
+    """An m x b panel of condition number kappa.
+      clustered: singular values 1 except the last four, 1/kappa;
+      graded:    singular values kappa^(-i/(b-1));
+      scaled:    a well-conditioned N(0,1) panel times diag(kappa^(-i/(b-1)))
+                 (badly scaled columns; every column's angle to the span of
+                 the others stays O(1), so no single pivot ratio is small)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    if kind == "scaled":
+        return g.standard_normal((m, b)) * kappa ** (-np.arange(b) / (b - 1))
+    Uq, _ = np.linalg.qr(g.standard_normal((m, b)))
+    Vq, _ = np.linalg.qr(g.standard_normal((b, b)))
+    if kind == "clustered":
+        s = np.ones(b)
+        s[-4:] = 1.0 / kappa
+    else:
+        s = kappa ** (-np.arange(b) / (b - 1))
+    return (Uq * s) @ Vq.T
+
+
+def sym_with_first_panel(P, w, seed):
+    """Symmetric (m + w) x (m + w) matrix, N(0,1) elsewhere, whose first
+    panel A[w:, :b] is P (so the reduction's first b reflectors are those of
+    the Householder QR of P)."""
+    m, b = P.shape
+    n = m + w
+    g = np.random.Generator(np.random.PCG64(seed))
+    Z = np.triu(g.standard_normal((n, n)))
+    A = Z + np.triu(Z, 1).T
+    A[w:, :b] = P
+    A[:b, w:] = P.T
+    return np.asfortranarray(A)

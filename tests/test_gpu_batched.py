@@ -2,7 +2,7 @@
 CPU oracle, matrix by matrix.
 
 Tolerances as for the single-matrix path: band entries within 1e-14 * n *
-||A||_F, reflector entries and tau within 1e-14 * n, FP64 backward error
+max|B|, reflector entries and tau within 1e-14 * n, FP64 backward error
 <= 1e-14 * n; the FP32-update form is held to a backward error <= 1e-5 * n.
 The X = A2 Wt accumulation of the batched kernel adds block contributions of
 different waves in arrival order, so two runs agree to rounding, not bit for
@@ -13,7 +13,7 @@ import pytest
 import torch
 
 from paper_1709_00302_amd import inputs, metrics
-from tests.gpu_util import sy_compare, to_device_colmajor
+from tests.gpu_util import sy_band_max, sy_compare, to_device_colmajor
 
 pytestmark = pytest.mark.gpu
 
@@ -70,8 +70,8 @@ def _check_against_oracle(orc, mats, dev, taus, w, pads=None, tol_scale=1e-14):
             continue
         db, dr, dt = sy_compare(np.tril(Ag), tg, np.tril(Ao), to, w)
         tol = tol_scale * n
-        nA = np.linalg.norm(A)
-        assert db <= tol * nA and dr <= tol and dt <= tol, (k, n, db, dr, dt, tol)
+        bmax = sy_band_max(np.tril(Ao), w)
+        assert db <= tol * bmax and dr <= tol and dt <= tol, (k, n, db, dr, dt, tol)
 
 
 @pytest.mark.parametrize("w,b", [(16, 16), (24, 8), (20, 16), (16, 5)])
@@ -204,7 +204,8 @@ def test_batched_graph_replay(bandred, orc):
             Ao, to = orc.sy2sb(A, w)
             db, dr, dt = sy_compare(np.tril(Ag), taus[k].cpu().numpy(), np.tril(Ao), to, w)
             tol = 1e-14 * n
-            assert db <= tol * np.linalg.norm(A) and dr <= tol and dt <= tol, (rep, k, db, dr, dt)
+            bmax = sy_band_max(np.tril(Ao), w)
+            assert db <= tol * bmax and dr <= tol and dt <= tol, (rep, k, db, dr, dt)
 
 
 def test_batched_banded_input_is_exact(bandred):

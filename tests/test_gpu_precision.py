@@ -1,0 +1,162 @@
+"""GPU checks of the two reduced-precision forms of the trailing update,
+through the C ABI, against the FP64 oracle and the known spectrum.
+
+  fp32     the trailing-update products run on FP32 MFMA with FP32
+           accumulation (operands rounded to FP32); panels, tau and T FP64.
+  split32  operands split as hi + lo FP32 pairs, three FP32 MFMA products,
+           partial sums folded into FP64 after every k slice of 16.
+
+The paper is FP64 only (Sec. 4); the bounds are those stated for the forms:
+backward error ||A - Q B Q^T||_F / ||A||_F <= 1e-5 n for the FP32 form and
+<= 1e-12 n for the split form.  Because the panels stay FP64, every reflector
+is orthogonal to FP64 accuracy whatever the update precision, so ||Q^T Q - I||
+and tau_c v_c^T v_c / 2 - 1 are held to the FP64 bar 1e-14 n.  The Householder
+structure must equal the oracle's: the same positions of tau = 0 and the same
+sign of every beta (the band entry each reflector creates).  Eigen- and
+singular values are checked against the known spectrum with Weyl's bound:
+|lambda_i(B) - lambda_i(A)| <= ||A - Q B Q^T||_2 <= backward * ||A||_F.
+
+Elementwise agreement of v and tau with the FP64 oracle is not a property of
+these forms (the panels factor columns perturbed at the FP32 level); the
+differences are printed, not gated.
+
+The split form does not reach its 1e-12 n bound on this hardware: gfx950 has
+no FP32-input MFMA with FP64 accumulation, so each 16-deep slice of the
+hi * hi product is rounded to FP32 before it reaches FP64.  That bound is
+kept as a strict expected failure (measured 9.4e-8 at n = 16384, against
+1.6e-8).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1709_00302_amd import inputs, metrics
+from tests.gpu_util import to_device_colmajor
+
+pytestmark = pytest.mark.gpu
+
+FORMS = ["fp32", "split32"]
+
+
+def _sy_case(n, seed):
+    g = inputs.rng(seed)
+    lam = inputs.uniform_lambda(n, g)
+    return inputs.sym_known(n, lam, g), lam
+
+
+def _sy_run(br, A, w, b, prec):
+    n = A.shape[0]
+    Ad, _ = to_device_colmajor(A, n)
+    tau = br.sy2sb(Ad, w, b, prec=prec)
+    torch.cuda.synchronize()
+    return np.tril(Ad.cpu().numpy()), tau.cpu().numpy()
+
+
+def _sy_structure(Ag, tg, Ao, to, w):
+    """Positions of tau = 0 and signs of beta equal to the oracle's."""
+    n = Ao.shape[0]
+    assert np.array_equal(tg == 0.0, to == 0.0)
+    c = np.arange(n - w - 1)
+    flips = int(np.sum(np.sign(Ag[c + w, c]) != np.sign(Ao[c + w, c])))
+    assert flips == 0, f"{flips} reflectors with a different beta sign"
+
+
+_sy_cache = {}
+
+
+def _sy_errors(br, orc, prec, n=2000, w=64, b=64, seed=81):
+    key = (prec, n, w, b, seed)
+    if key not in _sy_cache:
+        A, lam = _sy_case(n, seed)
+        Ag, tg = _sy_run(br, A, w, b, prec)
+        Ao, to = orc.sy2sb(A, w)
+        err = metrics.sy2sb_errors(A, Ag, tg, w, lam=lam)
+        _sy_cache[key] = (A, lam, Ag, tg, Ao, to, err)
+    return _sy_cache[key]
+
+
+@pytest.mark.parametrize("prec", FORMS)
+def test_sy2sb_form_bounds(bandred, orc, prec):
+    n, w = 2000, 64
+    print(f"case sy2sb precision {prec} n={n} w={w}", flush=True)
+    A, lam, Ag, tg, Ao, to, err = _sy_errors(bandred, orc, prec)
+    dv = np.abs(np.tril(Ag, -w - 1) - np.tril(Ao, -w - 1)).max()
+    print(f"  {prec}: {err}  max|v - v_oracle| {dv:.2e}  max|tau - tau_oracle| "
+          f"{np.abs(tg - to).max():.2e}", flush=True)
+    assert err["backward"] <= 1e-5 * n, err
+    assert err["orth"] <= 1e-14 * n, err
+    assert err["reflector_orth"] <= 1e-14 * n, err
+    assert err["band_trunc"] <= 1e-5 * n, err
+    nA = np.linalg.norm(A)
+    lmax = np.abs(lam).max()
+    assert err["eig_err"] * lmax <= err["backward"] * nA * (1 + 1e-6) + 1e-13, err
+    _sy_structure(Ag, tg, Ao, to, w)
+
+
+def test_sy2sb_split_beats_fp32(bandred, orc):
+    """The hi/lo split gains accuracy over the plain FP32 form."""
+    e32 = _sy_errors(bandred, orc, "fp32")[-1]["backward"]
+    esp = _sy_errors(bandred, orc, "split32")[-1]["backward"]
+    print(f"  backward fp32 {e32:.2e}  split32 {esp:.2e}  gain {e32 / esp:.1f}x", flush=True)
+    assert esp < 0.5 * e32
+
+
+@pytest.mark.xfail(strict=True, reason="FP32-accumulating MFMA caps the split form near 1e-8 "
+                                       "(9.4e-8 measured at n=16384 against 1.6e-8)")
+def test_sy2sb_split_meets_near_fp64_bound(bandred, orc):
+    n = 2000
+    err = _sy_errors(bandred, orc, "split32")[-1]
+    assert err["backward"] <= 1e-12 * n, err
+
+
+def _ge_case(m, n, seed):
+    g = inputs.rng(seed)
+    sig = inputs.logu_sigma(n, g)
+    return inputs.ge_known(m, n, sig, g), sig
+
+
+@pytest.mark.parametrize("prec", FORMS)
+def test_ge2gb_form_bounds(bandred, orc, prec):
+    m, n, w = 2000, 1500, 64
+    print(f"case ge2gb precision {prec} {m}x{n} w={w}", flush=True)
+    A, sig = _ge_case(m, n, 82)
+    Ad, _ = to_device_colmajor(A, m)
+    tq, tp = bandred.ge2gb(Ad, w, w, prec=prec)
+    torch.cuda.synchronize()
+    Ag, tqg, tpg = Ad.cpu().numpy(), tq.cpu().numpy(), tp.cpu().numpy()
+    Ao, tqo, tpo = orc.ge2gb(A, w)
+    err = metrics.ge2gb_errors(A, Ag, tqg, tpg, w, sigma=sig)
+    print(f"  {prec}: {err}", flush=True)
+    assert err["backward"] <= 1e-5 * m, err
+    assert err["orth"] <= 1e-14 * m, err
+    assert err["band_trunc"] <= 1e-5 * m, err
+    nA = np.linalg.norm(A)
+    assert err["sv_err"] * sig.max() <= err["backward"] * nA * (1 + 1e-6) + 1e-13, err
+    assert np.array_equal(tqg == 0.0, tqo == 0.0) and np.array_equal(tpg == 0.0, tpo == 0.0)
+    c = np.arange(n)
+    assert np.all(np.sign(Ag[c, c]) == np.sign(Ao[c, c]))
+    c = np.arange(n - w - 1)
+    assert np.all(np.sign(Ag[c, c + w]) == np.sign(Ao[c, c + w]))
+
+
+@pytest.mark.parametrize("prec", FORMS)
+def test_sy2sb_full_size_forms(bandred, prec):
+    """The n = 16384, w = b = 128 graded-spectrum workload in both forms, as
+    the bench times them (look-ahead, eager calls): backward error by random
+    probes, every reflector orthogonal, every tau nonzero."""
+    name = "sy2sb_n16384_w128"
+    print(f"case {name} {prec}: building the input on the GPU", flush=True)
+    p = inputs.make_on_device(name, device="cuda")
+    A0, n, w, b = p["A"], p["n"], p["w"], p["b"]
+    A = A0.clone(memory_format=torch.preserve_format)
+    tau = bandred.sy2sb(A, w, b, prec=prec)
+    torch.cuda.synchronize()
+    err = metrics.sy2sb_errors(A0, torch.tril(A), tau, w, eig=False)
+    print(f"case {name} {prec}: {err}", flush=True)
+    assert err["backward"] <= 1e-5 * n, err
+    assert err["reflector_orth"] <= 1e-14 * n, err
+    assert bool(torch.all(tau[: n - w - 1] != 0.0))
+    if prec == "split32":
+        # recorded beside the strict expected failure above
+        print(f"case {name} split32: backward / (1e-12 n) = "
+              f"{err['backward'] / (1e-12 * n):.1f}", flush=True)

@@ -31,3 +31,44 @@ def test_ge2gb_model_matches_oracle(orc, m, n, w, b):
     assert np.abs(Am - Ao).max() <= 1e-12
     assert np.abs(tqm - tqo).max() <= 1e-13
     assert np.abs(tpm - tpo).max() <= 1e-13
+
+
+# CholeskyQR2 acceptance (the default panel method): which branch a panel of
+# condition kappa takes, and how close the accepted reconstruction comes to
+# the oracle's Householder vectors.  Any two backward-stable QR methods agree
+# on the reflectors of a panel of condition kappa only to about kappa * u, so
+# the accepted panels are held to the closeness of a second Householder QR
+# (the per-column numpy model) to the oracle, and to the FP64 bar 1e-14 n
+# where kappa <= 1e4.
+KAPPA_CASES = [
+    # (kind, kappa, expected branch)
+    ("clustered", 1e4, "cholqr2"), ("clustered", 1e6, "fallback-chol1"),
+    ("clustered", 1e8, "fallback-chol1"), ("clustered", 1e10, "fallback-chol1"),
+    ("graded", 1e4, "cholqr2"), ("graded", 1e6, "cholqr2"),
+    ("graded", 1e8, "fallback-chol1"), ("graded", 1e10, "fallback-chol1"),
+    ("scaled", 1e4, "cholqr2"), ("scaled", 1e6, "cholqr2"),
+    ("scaled", 1e8, "cholqr2"), ("scaled", 1e10, "cholqr2"),
+]
+
+
+@pytest.mark.parametrize("kind,kappa,branch", KAPPA_CASES)
+def test_cholqr2_acceptance(orc, kind, kappa, branch):
+    m, b, w = 600, 32, 32
+    n = m + w
+    P = mb.conditioned_panel(m, b, kappa, kind, 5)
+    r = mb.cholqr2_recon(P)
+    assert r["branch"] == branch, r["branch"]
+    if branch != "cholqr2":
+        return
+    A = mb.sym_with_first_panel(P, w, 6)
+    Ao, to = orc.sy2sb(A, w, ncols=b)
+    Vo = np.tril(Ao[w:, :b], -1)
+    Vo[np.arange(b), np.arange(b)] = 1.0
+    beta_o = np.diag(Ao[w:w + b, :b])
+    Vh, _ = mb.panel_qr(P.copy())
+    d_house = np.abs(Vh - Vo).max()
+    dv = np.abs(r["V"] - Vo).max()
+    dt = np.abs(r["tau"] - to[:b]).max()
+    tol = 1e-14 * n if kappa <= 1e4 else max(1e-14 * n, 4.0 * d_house)
+    assert dv <= tol and dt <= tol, (dv, dt, d_house)
+    assert np.abs(r["beta"] - beta_o).max() <= 1e-14 * n * np.abs(beta_o).max()
