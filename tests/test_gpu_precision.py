@@ -133,10 +133,17 @@ def test_ge2gb_form_bounds(bandred, orc, prec):
     nA = np.linalg.norm(A)
     assert err["sv_err"] * sig.max() <= err["backward"] * nA * (1 + 1e-6) + 1e-13, err
     assert np.array_equal(tqg == 0.0, tqo == 0.0) and np.array_equal(tpg == 0.0, tpo == 0.0)
-    c = np.arange(n)
-    assert np.all(np.sign(Ag[c, c]) == np.sign(Ao[c, c]))
-    c = np.arange(n - w - 1)
-    assert np.all(np.sign(Ag[c, c + w]) == np.sign(Ao[c, c + w]))
+    # With sigma down to 1e-8 the trailing matrix of the last steps is smaller
+    # than the form's own perturbation (backward * ||A||_F): there beta is
+    # made of rounding and its sign is not determined.  Every beta above that
+    # level (with a factor 10 of margin) has the oracle's sign.
+    floor = 10.0 * err["backward"] * nA
+    for d, name in ((np.arange(n), "left"), (np.arange(n - w - 1), "right")):
+        cols = d + (w if name == "right" else 0)
+        bo, bg = Ao[d, cols], Ag[d, cols]
+        big = np.abs(bo) > floor
+        print(f"  {name} betas above {floor:.1e}: {int(big.sum())} of {len(d)}", flush=True)
+        assert np.all(np.sign(bg[big]) == np.sign(bo[big])), name
 
 
 @pytest.mark.parametrize("prec", FORMS)
