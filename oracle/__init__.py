@@ -6,9 +6,12 @@ library (``paper_1709_00302_amd``) neither imports nor links it; the two
 share no code.
 
 ``sy2sb`` follows Sec. 2.1 of the paper (reduction of a symmetric matrix to
-symmetric band form, eqs. updateA0..updateA2syr2k at block size 1) and
+symmetric band form, eqs. updateA0..updateA2syr2k at block size 1),
 ``ge2gb`` follows Sec. 3.1 (reduction of a general matrix to upper
-triangular-band form, eqs. updateB..updateD at block size 1).  The arithmetic
+triangular-band form, eqs. updateB..updateD at block size 1), ``ge2gb_lu``
+Sec. 3.3 (band form with equal lower and upper bandwidth, eqs.
+updateB0..updateCD22 at block size 1), and ``apply_refl`` applies the
+stored reflectors of any of them (the back-transformation).  The arithmetic
 lives in ``oracle.c``; this module only marshals numpy arrays.
 """
 from __future__ import annotations
@@ -54,6 +57,12 @@ class Oracle:
         lib.oracle_ge2gb.argtypes = [_c_i64, _c_i64, _c_i64, _c_i64, _c_dp, _c_i64,
                                      _c_dp, _c_dp]
         lib.oracle_ge2gb.restype = ctypes.c_int
+        lib.oracle_ge2gb_lu.argtypes = [_c_i64, _c_i64, _c_i64, _c_i64, _c_dp, _c_i64,
+                                        _c_dp, _c_dp]
+        lib.oracle_ge2gb_lu.restype = ctypes.c_int
+        lib.oracle_apply_refl.argtypes = [ctypes.c_int, _c_i64, _c_i64, _c_i64, _c_dp, _c_i64,
+                                          _c_dp, ctypes.c_int, _c_i64, _c_dp, _c_i64]
+        lib.oracle_apply_refl.restype = ctypes.c_int
         lib.oracle_house.argtypes = [_c_i64, _c_dp, _c_i64, _c_dp]
         lib.oracle_house.restype = ctypes.c_double
         lib.oracle_threads.argtypes = []
@@ -121,6 +130,59 @@ class Oracle:
         if info != 0:
             raise ValueError(f"oracle_ge2gb returned {info}")
         return Aout, tauq[:n], taup[:n]
+
+    def ge2gb_lu(self, A, w: int, ncols: int = -1):
+        """Reduce general ``A`` (m >= n) to band form with lower and upper
+        bandwidth ``w`` (Sec. 3.3).  Returns (Aout, tauq, taup), each tau of
+        length n."""
+        A = np.asarray(A, dtype=np.float64)
+        m, n = A.shape
+        Aout = np.array(A, dtype=np.float64, order="F", copy=True)
+        tauq = np.zeros(max(n, 1), dtype=np.float64)
+        taup = np.zeros(max(n, 1), dtype=np.float64)
+        info = self.lib.oracle_ge2gb_lu(m, n, w, ncols, self._ptr(Aout), max(m, 1),
+                                        self._ptr(tauq), self._ptr(taup))
+        if info != 0:
+            raise ValueError(f"oracle_ge2gb_lu returned {info}")
+        return Aout, tauq[:n], taup[:n]
+
+    def apply_refl(self, Aout, tau, rowstore: bool, off: int, nrefl: int, C,
+                   trans: bool = False):
+        """Q C (or Q^T C) for the stored reflectors of a reduction (see
+        oracle.h: which rowstore / off / nrefl each factor uses)."""
+        Aout = np.asarray(Aout, dtype=np.float64, order="F")
+        tau = np.ascontiguousarray(tau, dtype=np.float64)
+        C = np.array(C, dtype=np.float64, order="F", copy=True)
+        if C.ndim == 1:
+            C = C[:, None]
+        length, k = C.shape
+        tbuf = np.zeros(max(nrefl, 1), dtype=np.float64)
+        tbuf[:nrefl] = tau[:nrefl]
+        info = self.lib.oracle_apply_refl(1 if rowstore else 0, off, nrefl, length,
+                                          self._ptr(Aout), max(Aout.shape[0], 1),
+                                          self._ptr(tbuf), 1 if trans else 0, k, self._ptr(C),
+                                          max(length, 1))
+        if info != 0:
+            raise ValueError(f"oracle_apply_refl returned {info}")
+        return C
+
+    def sy2sb_q(self, Aout, tau, w: int, C, trans: bool = False):
+        """Q C or Q^T C for the result of ``sy2sb``."""
+        n = Aout.shape[0]
+        return self.apply_refl(Aout, tau, False, w, max(n - w, 0), C, trans)
+
+    def ge2gb_u(self, Aout, tauq, w: int, C, trans: bool = False, equal_band: bool = False):
+        """U C or U^T C for the result of ``ge2gb`` (or ``ge2gb_lu``)."""
+        m, n = Aout.shape
+        if equal_band:
+            return self.apply_refl(Aout, tauq, False, w, min(n, max(m - w, 0)), C, trans)
+        return self.apply_refl(Aout, tauq, False, 0, n, C, trans)
+
+    def ge2gb_v(self, Aout, taup, w: int, C, trans: bool = False):
+        """V C or V^T C for the result of ``ge2gb`` or ``ge2gb_lu`` (both
+        store the right reflectors the same way)."""
+        m, n = Aout.shape
+        return self.apply_refl(Aout, taup, True, w, max(n - w, 0), C, trans)
 
     # raw entry points with explicit sizes, for argument-check tests
     def raw_sy2sb(self, n, w, ncols, A, lda, tau):

@@ -30,6 +30,10 @@
  * sum is accumulated by one thread in a fixed order, so results do not depend
  * on the thread count.
  *
+ * Also: ge2gb_lu (Sec. 3.3, band form with equal lower and upper bandwidth,
+ * eqs. updateB0..updateCD22 at block size 1) and apply_refl (the product of
+ * the stored reflectors applied to a matrix, the back-transformation).
+ *
  * ORACLE_MUTANT (compile-time, default 0) plants one deliberate mistake; the
  * test-suite builds such variants to show that its pins catch them.  A normal
  * build never defines it.
@@ -298,5 +302,163 @@ int oracle_ge2gb(int64_t m, int64_t n, int64_t w, int64_t ncols, double *A,
     }
   }
   free(u); free(s);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* General matrix to band form with equal lower and upper bandwidth         */
+/* ------------------------------------------------------------------------ */
+
+/* Sec. 3.3 (eqs. updateB0..updateCD22) at block size 1.  Step c: the left
+ * reflector of column c annihilates rows c+w+1 .. m-1 of that column and is
+ * applied from the left to the columns right of it (rows c+w .. m-1); the
+ * right reflector of row c annihilates columns c+w+1 .. n-1 of that row and
+ * is applied from the right to the rows below it (columns c+w .. n-1).  The
+ * two reflectors of one step touch disjoint parts of each other's vector
+ * (rows >= c+w versus row c, columns >= c+w versus column c), so their order
+ * within a step does not matter; the left one is taken first. */
+int oracle_ge2gb_lu(int64_t m, int64_t n, int64_t w, int64_t ncols, double *A,
+                    int64_t lda, double *tauq, double *taup) {
+  if (m < 0) return -1;
+  if (n < 0) return -2;
+  if (m < n) return -1;
+  if (w < 1) return -3;
+  if (n > 0 && A == NULL) return -5;
+  if (lda < (m > 1 ? m : 1)) return -6;
+  if (n > 0 && tauq == NULL) return -7;
+  if (n > 0 && taup == NULL) return -8;
+  if (n == 0) return 0;
+
+  for (int64_t c = 0; c < n; ++c) tauq[c] = taup[c] = 0.0;
+  int64_t nsteps = n;
+  if (ncols >= 0 && ncols < nsteps) nsteps = ncols;
+
+  double *u = (double *)malloc(sizeof(double) * (size_t)(m > n ? m : n));
+  double *s = (double *)malloc(sizeof(double) * (size_t)m);
+  if (!u || !s) {
+    free(u); free(s);
+    return 2;
+  }
+
+  for (int64_t c = 0; c < nsteps; ++c) {
+    /* left reflector: column c, rows c+w .. m-1 */
+    const int64_t r = c + w;
+    if (r < m) {
+      const int64_t L = m - r;
+      double beta;
+      double tq = oracle_house(L, A + r + c * lda, 1, &beta);
+      u[0] = 1.0;
+      for (int64_t i = 1; i < L; ++i) u[i] = A[r + i + c * lda];
+      if (tq != 0.0) {
+#if ORACLE_MUTANT == 8
+        const int64_t j0 = (c + w < n) ? c + w : n; /* planted: in-band columns skipped */
+#else
+        const int64_t j0 = c + 1;
+#endif
+#pragma omp parallel for schedule(static)
+        for (int64_t j = j0; j < n; ++j) {
+          double *col = A + r + j * lda;
+          double d = 0.0;
+          for (int64_t i = 0; i < L; ++i) d += u[i] * col[i];
+          const double f = tq * d;
+          for (int64_t i = 0; i < L; ++i) col[i] -= f * u[i];
+        }
+      }
+      A[r + c * lda] = beta;
+      tauq[c] = tq;
+    }
+    /* right reflector: row c, columns c+w .. n-1 */
+    const int64_t c0 = c + w;
+    if (c0 < n) {
+      const int64_t L = n - c0;
+      double gamma;
+      double tp = oracle_house(L, A + c + c0 * lda, lda, &gamma);
+      u[0] = 1.0;
+      for (int64_t k = 1; k < L; ++k) u[k] = A[c + (c0 + k) * lda];
+      if (tp != 0.0) {
+#if ORACLE_MUTANT == 7
+        const int64_t r0 = (c + w < m) ? c + w : m; /* planted: rows c+1..c+w-1 skipped */
+#else
+        const int64_t r0 = c + 1;
+#endif
+        const int64_t nr = m - r0;
+        int nt = oracle_threads();
+        int64_t chunk = (nr + nt - 1) / nt;
+        if (chunk < 64) chunk = 64;
+#pragma omp parallel for schedule(static)
+        for (int64_t r1 = 0; r1 < nr; r1 += chunk) {
+          const int64_t r2 = (r1 + chunk < nr) ? r1 + chunk : nr;
+          double *sr = s + r0;
+          for (int64_t q = r1; q < r2; ++q) sr[q] = 0.0;
+          for (int64_t k = 0; k < L; ++k) {
+            const double *col = A + r0 + (c0 + k) * lda;
+            const double uk = u[k];
+            for (int64_t q = r1; q < r2; ++q) sr[q] += col[q] * uk;
+          }
+          for (int64_t k = 0; k < L; ++k) {
+            double *col = A + r0 + (c0 + k) * lda;
+            const double f = tp * u[k];
+            for (int64_t q = r1; q < r2; ++q) col[q] -= sr[q] * f;
+          }
+        }
+      }
+      A[c + c0 * lda] = gamma;
+      taup[c] = tp;
+    }
+  }
+  free(u); free(s);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Applying the stored reflectors (back-transformation)                      */
+/* ------------------------------------------------------------------------ */
+
+/* The orthogonal factor of a reduction is the product of its reflectors
+ * taken in the order they were made, Q = H_0 H_1 ... H_{nrefl-1} (Sec. 2.1
+ * and Sec. 3: Q is accumulated as I + W Y^T panel by panel).  Reflector i acts
+ * on indices i+off .. len-1 with v[0] = 1 at index i+off and v[t] (t >= 1)
+ * stored at A(i+off+t, i) (column storage) or A(i, i+off+t) (row storage).
+ * trans = 0: C := Q C; trans = 1: C := Q^T C = H_{nrefl-1} ... H_0 C, for the
+ * len x k matrix C (ld ldc).  One reflector at a time, each column of C on its
+ * own (OpenMP over the columns of C). */
+int oracle_apply_refl(int rowstore, int64_t off, int64_t nrefl, int64_t len,
+                      const double *A, int64_t lda, const double *tau, int trans,
+                      int64_t k, double *C, int64_t ldc) {
+  if (off < 0) return -2;
+  if (nrefl < 0 || nrefl + off > len) return -3;
+  if (len < 0) return -4;
+  if (nrefl > 0 && A == NULL) return -5;
+  if (nrefl > 0 && tau == NULL) return -7;
+  if (trans != 0 && trans != 1) return -8;
+  if (k < 0) return -9;
+  if (k > 0 && len > 0 && C == NULL) return -10;
+  if (ldc < (len > 1 ? len : 1)) return -11;
+  if (nrefl == 0 || k == 0) return 0;
+  double *v = (double *)malloc(sizeof(double) * (size_t)len);
+  if (!v) return 2;
+  for (int64_t step = 0; step < nrefl; ++step) {
+#if ORACLE_MUTANT == 9
+    const int64_t i = step; /* planted: Q C applied in the order of Q^T C */
+    (void)trans;
+#else
+    const int64_t i = trans ? step : nrefl - 1 - step;
+#endif
+    const double t = tau[i];
+    if (t == 0.0) continue;
+    const int64_t r = i + off, L = len - r;
+    v[0] = 1.0;
+    for (int64_t q = 1; q < L; ++q)
+      v[q] = rowstore ? A[i + (r + q) * lda] : A[(r + q) + i * lda];
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < k; ++j) {
+      double *col = C + r + j * ldc;
+      double d = 0.0;
+      for (int64_t q = 0; q < L; ++q) d += v[q] * col[q];
+      const double f = t * d;
+      for (int64_t q = 0; q < L; ++q) col[q] -= f * v[q];
+    }
+  }
+  free(v);
   return 0;
 }

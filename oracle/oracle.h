@@ -41,6 +41,32 @@ int oracle_sy2sb(int64_t n, int64_t w, int64_t ncols, double *A, int64_t lda,
 int oracle_ge2gb(int64_t m, int64_t n, int64_t w, int64_t ncols, double *A,
                  int64_t lda, double *tauq, double *taup);
 
+/* General m x n matrix, m >= n, to band form with lower AND upper bandwidth w
+ * (Sec. 3.3).  Processes steps c = 0 .. min(ncols, n)-1 (ncols < 0: all).
+ * Step c: left reflector of column c acting on rows c+w..m-1 (beta at
+ * (c+w, c), v[1:] below it, scalar tauq[c]; only when c+w < m), then right
+ * reflector of row c acting on columns c+w..n-1 (gamma at (c, c+w), u[1:] to
+ * its right, scalar taup[c]; only when c+w < n).  tauq and taup have n
+ * entries each; entries with no reflector (or a length-1 one) are 0.  On
+ * return B(i,j) for -w <= j-i <= w holds the band; U = H_0 H_1 ...,
+ * V = G_0 G_1 ..., B = U^T A V. */
+int oracle_ge2gb_lu(int64_t m, int64_t n, int64_t w, int64_t ncols, double *A,
+                    int64_t lda, double *tauq, double *taup);
+
+/* C := Q C (trans = 0) or Q^T C (trans = 1) for Q = H_0 H_1 ... H_{nrefl-1}
+ * made of stored reflectors (back-transformation).  Reflector i acts on
+ * indices i+off .. len-1; its vector has v[0] = 1 implicit at index i+off
+ * and v[t], t >= 1, at A(i+off+t, i) (rowstore = 0) or A(i, i+off+t)
+ * (rowstore = 1); tau[i] its scalar.  C is len x k, column-major, ld ldc.
+ *   sy2sb Q:      rowstore 0, off w, nrefl n-w, len n
+ *   ge2gb U:      rowstore 0, off 0, nrefl n, len m
+ *   ge2gb V:      rowstore 1, off w, nrefl max(0, n-w), len n
+ *   ge2gb_lu U:   rowstore 0, off w, nrefl min(n, max(0, m-w)), len m
+ *   ge2gb_lu V:   rowstore 1, off w, nrefl max(0, n-w), len n */
+int oracle_apply_refl(int rowstore, int64_t off, int64_t nrefl, int64_t len,
+                      const double *A, int64_t lda, const double *tau, int trans,
+                      int64_t k, double *C, int64_t ldc);
+
 /* Householder vector of x (length L, stride inc): on return x[0] is left
  * alone, x[1:] holds v[1:], *beta the new leading entry; returns tau. */
 double oracle_house(int64_t L, double *x, int64_t inc, double *beta);

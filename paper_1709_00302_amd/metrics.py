@@ -150,50 +150,60 @@ def sy2sb_errors(A, Aout, tau, w: int, lam=None, explicit_max: int = 2048,
 # general -> upper triangular-band
 # --------------------------------------------------------------------------
 
-def ge_band_dense(Aout: torch.Tensor, w: int) -> torch.Tensor:
+def ge_band_dense(Aout: torch.Tensor, w: int, lower: int = 0) -> torch.Tensor:
+    """Dense band B (-lower <= j-i <= w) of Aout: lower = 0 for the upper
+    triangular-band form, lower = w for the equal-bandwidth form."""
     m, n = Aout.shape
     i = torch.arange(m, device=Aout.device)[:, None]
     j = torch.arange(n, device=Aout.device)[None, :]
-    keep = (j - i >= 0) & (j - i <= w)
+    keep = (j - i >= -lower) & (j - i <= w)
     return torch.where(keep, Aout, torch.zeros((), dtype=f64, device=Aout.device))
 
 
-def ge_band_matvec(Aout: torch.Tensor, w: int, X: torch.Tensor) -> torch.Tensor:
-    """B @ X for the m x n upper triangular-band B stored in Aout."""
+def ge_band_matvec(Aout: torch.Tensor, w: int, X: torch.Tensor, lower: int = 0) -> torch.Tensor:
+    """B @ X for the m x n band B (-lower <= j-i <= w) stored in Aout."""
     m, n = Aout.shape
     Y = torch.zeros(m, X.shape[1], dtype=f64, device=X.device)
-    for d in range(0, min(w, n - 1) + 1):
-        diag = torch.diagonal(Aout, offset=d)  # B[i, i+d], i = 0 .. n-d-1
+    for d in range(-min(lower, m - 1), min(w, n - 1) + 1):
+        diag = torch.diagonal(Aout, offset=d)  # B[i, i+d]
         k = diag.shape[0]
-        Y[:k] += diag[:, None] * X[d:d + k]
+        if d >= 0:
+            Y[:k] += diag[:, None] * X[d:d + k]
+        else:
+            Y[-d:-d + k] += diag[:, None] * X[:k]
     return Y
 
 
-def ge_band_rmatvec(Aout: torch.Tensor, w: int, X: torch.Tensor) -> torch.Tensor:
+def ge_band_rmatvec(Aout: torch.Tensor, w: int, X: torch.Tensor, lower: int = 0) -> torch.Tensor:
     """B^T @ X (X has m rows)."""
     m, n = Aout.shape
     Y = torch.zeros(n, X.shape[1], dtype=f64, device=X.device)
-    for d in range(0, min(w, n - 1) + 1):
+    for d in range(-min(lower, m - 1), min(w, n - 1) + 1):
         diag = torch.diagonal(Aout, offset=d)
         k = diag.shape[0]
-        Y[d:d + k] += diag[:, None] * X[:k]
+        if d >= 0:
+            Y[d:d + k] += diag[:, None] * X[:k]
+        else:
+            Y[:k] += diag[:, None] * X[-d:-d + k]
     return Y
 
 
-def apply_u(Aout, tauq, X, transpose=False):
+def apply_u(Aout, tauq, X, transpose=False, off: int = 0):
     """U X (or U^T X), U = H_0 ... H_{n-1}; left reflector c acts on rows
-    c .. m-1 with v = [1; Aout[c+1:, c]]."""
+    c+off .. m-1 with v = [1; Aout[c+off+1:, c]] (off = 0 for the upper
+    triangular-band form, off = w for the equal-bandwidth form)."""
     X = X.clone()
+    m = Aout.shape[0]
     n = tauq.shape[0]
     taus = tauq.tolist()
     order = range(n) if transpose else range(n - 1, -1, -1)
     for c in order:
         t = taus[c]
-        if t == 0.0:
+        if t == 0.0 or c + off >= m:
             continue
-        v = Aout[c:, c].clone()
+        v = Aout[c + off:, c].clone()
         v[0] = 1.0
-        X[c:] -= t * torch.outer(v, v @ X[c:])
+        X[c + off:] -= t * torch.outer(v, v @ X[c + off:])
     return X
 
 
@@ -216,7 +226,9 @@ def apply_v(Aout, taup, w, X, transpose=False):
 
 
 def ge2gb_errors(A, Aout, tauq, taup, w: int, sigma=None, explicit_max: int = 2048,
-                 probes: int = 8, seed: int = 1234, svd: bool = True) -> dict:
+                 probes: int = 8, seed: int = 1234, svd: bool = True, lower: int = 0) -> dict:
+    """Errors of an upper triangular-band result (lower = 0) or of an
+    equal-bandwidth one (lower = w: left reflectors start w rows down)."""
     A = _t(A)
     Aout = _t(Aout, A.device)
     tauq = _t(tauq, A.device)
@@ -226,16 +238,16 @@ def ge2gb_errors(A, Aout, tauq, taup, w: int, sigma=None, explicit_max: int = 20
     out = {}
     sv = None
     if m <= explicit_max:
-        U = apply_u(Aout, tauq, torch.eye(m, dtype=f64, device=A.device))
+        U = apply_u(Aout, tauq, torch.eye(m, dtype=f64, device=A.device), off=lower)
         V = apply_v(Aout, taup, w, torch.eye(n, dtype=f64, device=A.device))
-        B = ge_band_dense(Aout, w)
+        B = ge_band_dense(Aout, w, lower)
         out["backward"] = float(torch.linalg.norm(A - U @ B @ V.T)) / nA
         out["orth"] = max(float(torch.linalg.norm(U.T @ U - torch.eye(m, dtype=f64, device=A.device))),
                           float(torch.linalg.norm(V.T @ V - torch.eye(n, dtype=f64, device=A.device))))
         C = U.T @ A @ V
         i = torch.arange(m, device=A.device)[:, None]
         j = torch.arange(n, device=A.device)[None, :]
-        off = ~((j - i >= 0) & (j - i <= w))
+        off = ~((j - i >= -lower) & (j - i <= w))
         out["band_trunc"] = float(torch.linalg.norm(C[off])) / nA
         if svd:
             sv = torch.linalg.svdvals(B)
@@ -244,8 +256,8 @@ def ge2gb_errors(A, Aout, tauq, taup, w: int, sigma=None, explicit_max: int = 20
         g.manual_seed(seed)
         X = torch.randn(n, probes, generator=g, dtype=f64, device=A.device)
         Y = apply_v(Aout, taup, w, X, transpose=True)
-        Y = ge_band_matvec(Aout, w, Y)
-        Y = apply_u(Aout, tauq, Y)
+        Y = ge_band_matvec(Aout, w, Y, lower)
+        Y = apply_u(Aout, tauq, Y, off=lower)
         E = A @ X - Y
         out["backward"] = float(torch.linalg.norm(E)) / math.sqrt(probes) / nA
         out["orth"] = None
