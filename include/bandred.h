@@ -124,6 +124,25 @@ BANDRED_API int bandred_ge2gb_ex(int64_t m, int64_t n, int64_t w, int64_t b, dou
                      int64_t lda, double *tauq, double *taup, int prec,
                      const bandred_opts_t *opts, void *stream);
 
+/* For callers that cannot allocate device memory: code under HIP stream
+ * capture with no earlier eager call, serving loops that must not allocate,
+ * harnesses that forbid hipMalloc.  Same reduction and arguments as
+ * bandred_sy2sb_ex (args 1-7 and stream, arg 8) run in the serial order (no
+ * look-ahead stream, no events), with the workspace in a fixed 64 MiB device
+ * array that the library holds on each device it runs on until the process
+ * ends.  The call allocates nothing: no hipMalloc, hipFree or allocating
+ * library routine.  The workspace it needs is about
+ * (n - w) * (120 b + b^2 / 8) bytes plus O(b^2 + b w): n <= 3455 at
+ * w = b = 128, n <= 8092 at w = b = 64, n <= 16607 at w = b = 32; a larger
+ * problem returns BANDRED_ERR_UNSUPPORTED before any work is enqueued (as
+ * does a call while profiling is enabled).  Every call on a device shares
+ * that device's array and leaves its contents behind (each call clears what
+ * it needs zeroed before use): calls that overlap on one device, on any
+ * streams, race and give undefined results; the caller orders them.
+ * Asynchronous; runtime failures are reported by bandred_status. */
+BANDRED_API int bandred_sy2sb_noalloc(int64_t n, int64_t w, int64_t b, double *A,
+                          int64_t lda, double *tau, int prec, void *stream);
+
 /* Many independent symmetric matrices of uneven orders reduced in one
  * persistent launch (not in the paper; same per-matrix result as
  * bandred_sy2sb).

@@ -64,6 +64,7 @@ def load(path: str = LIB_PATH):
                                      ctypes.POINTER(Opts), _vp]
     lib.bandred_ge2gb_ex.argtypes = [_i64, _i64, _i64, _i64, _vp, _i64, _vp, _vp, ctypes.c_int,
                                      ctypes.POINTER(Opts), _vp]
+    lib.bandred_sy2sb_noalloc.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, ctypes.c_int, _vp]
     lib.bandred_sy2sb_batched.argtypes = [_i64, ctypes.POINTER(_i64), _i64, _i64,
                                           ctypes.POINTER(_vp), ctypes.POINTER(_i64),
                                           ctypes.POINTER(_vp), ctypes.c_int, _vp]
@@ -77,7 +78,8 @@ def load(path: str = LIB_PATH):
     lib.bandred_profile_name.argtypes = [ctypes.c_int]
     lib.bandred_profile_name.restype = ctypes.c_char_p
     for name in ("bandred_sy2sb", "bandred_ge2gb", "bandred_sy2sb_ex", "bandred_ge2gb_ex",
-                 "bandred_sy2sb_batched", "bandred_profile_enable", "bandred_profile_read",
+                 "bandred_sy2sb_batched", "bandred_sy2sb_noalloc", "bandred_profile_enable",
+                 "bandred_profile_read",
                  "bandred_status", "bandred_set_wait_limit_us", "bandred_release"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -112,6 +114,10 @@ def bandred_sy2sb_ex(n, w, b, A, lda, tau, prec=FP64, opts=None, stream=None) ->
 def bandred_ge2gb_ex(m, n, w, b, A, lda, tauq, taup, prec=FP64, opts=None, stream=None) -> int:
     return load().bandred_ge2gb_ex(m, n, w, b, A, lda, tauq, taup, prec,
                                    ctypes.byref(opts) if opts is not None else None, stream)
+
+
+def bandred_sy2sb_noalloc(n, w, b, A, lda, tau, prec=FP64, stream=None) -> int:
+    return load().bandred_sy2sb_noalloc(n, w, b, A, lda, tau, prec, stream)
 
 
 def bandred_sy2sb_batched(count, n, w, b, A, lda, tau, prec=FP64, stream=None) -> int:

@@ -125,6 +125,9 @@ struct DevState {
 };
 static std::mutex g_mu;
 static DevState g_dev[64];
+// status words of the most recent call on each device (the library's own, or
+// those inside the no-allocation scratch)
+static int *g_last_flags[64];
 
 // Device properties only: no stream, event or memory is created.
 static int dev_props(DevState &st, int dev) {
@@ -146,6 +149,12 @@ static int current_device(int *dev) {
   BR_HIP_CHECK(hipGetDevice(dev));
   if (*dev < 0 || *dev >= 64) return BANDRED_ERR_UNSUPPORTED;
   return 0;
+}
+
+// index of the current device (valid once dev_state or dev_props succeeded)
+static int current_dev_index() {
+  int dev = 0;
+  return current_device(&dev) == 0 ? dev : 0;
 }
 
 static int dev_state(DevState **out) {
@@ -621,6 +630,7 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
   rc = launch_fill_u32((unsigned *)pstruct, (int64_t)(npan + 1) * 2 * kNbMax, 0u, s);
   if (rc) return rc;
   rc = launch_fill_u32((unsigned *)st->flags, 2, 0u, s); if (rc) return rc;
+  g_last_flags[current_dev_index()] = st->flags;
   rc = launch_fill(tau, n - w, 0.0, s); if (rc) return rc;
 
   // panel `it` (columns c .. c+pb-1) and its Wt = V T, on stream q
@@ -762,6 +772,7 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
   rc = launch_fill_u32((unsigned *)pstruct, (int64_t)(2 * npan + 2) * 2 * kNbMax, 0u, s);
   if (rc) return rc;
   rc = launch_fill_u32((unsigned *)st->flags, 2, 0u, s); if (rc) return rc;
+  g_last_flags[current_dev_index()] = st->flags;
   rc = launch_fill(tauq, n, 0.0, s); if (rc) return rc;
   rc = launch_fill(taup, n, 0.0, s); if (rc) return rc;
 
@@ -978,6 +989,9 @@ static int batched_impl(int64_t count, const int64_t *n, int w, int b, double *c
     }
     rc = launch_fill_u32(st->bt_queue, 1, 0u, s);
     if (rc) return rc;
+    rc = launch_fill_u32((unsigned *)st->flags, 2, 0u, s);  // no bounded waits: stays 0
+    if (rc) return rc;
+    g_last_flags[current_dev_index()] = st->flags;
     double flops = 0.0;
     for (const BatchEntry &e : tab) flops += 4.0 / 3.0 * (double)e.n * e.n * e.n;
     {
@@ -998,13 +1012,55 @@ static int batched_impl(int64_t count, const int64_t *n, int w, int b, double *c
 // Device status word of the most recent call on the current device (0, or
 // BANDRED_ERR_TIMEOUT), after the work on stream s has finished.
 static int read_status(hipStream_t s) {
-  DevState *st = nullptr;
-  int rc = dev_state(&st);
+  int dev = 0;
+  int rc = current_device(&dev);
   if (rc) return rc;
   BR_HIP_CHECK(hipStreamSynchronize(s));
+  if (!g_last_flags[dev]) return 0;  // no call on this device yet
   int flags[2] = {0, 0};
-  BR_HIP_CHECK(hipMemcpy(flags, st->flags, sizeof(flags), hipMemcpyDeviceToHost));
+  BR_HIP_CHECK(hipMemcpy(flags, g_last_flags[dev], sizeof(flags), hipMemcpyDeviceToHost));
   return flags[0];
+}
+
+// ---------------------------------------------------------------------------
+// No-allocation SY2SB.  The workspace is a fixed device array (one copy per
+// device, alive until the process ends): the first 256 bytes hold the status
+// words, the rest the arena that the library's own workspace would provide.
+// Runs the serial order (no look-ahead stream, no events), so it can be
+// called where allocation is impossible (under stream capture with no earlier
+// eager call, or in loops that must not allocate).
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+struct NoAllocDev {
+  bool ready = false;
+  DevState st;  // props, flags and arena inside the device copy of scratch
+};
+static NoAllocDev g_na[64];
+
+// Device address of this device's copy of scratch (looked up once per device,
+// with that device current), wrapped as a DevState without streams or events.
+static int noalloc_state(DevState **out) {
+  int dev = 0;
+  int rc = current_device(&dev);
+  if (rc) return rc;
+  NoAllocDev &na = g_na[dev];
+  if (!na.ready) {
+    rc = dev_props(na.st, dev);
+    if (rc) return rc;
+    void *p = nullptr;
+    BR_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (p == nullptr) return BANDRED_ERR_HIP;
+    na.st.flags = reinterpret_cast<int *>(p);
+    na.st.base = reinterpret_cast<char *>(p) + 256;
+    na.st.bytes = kNoAllocBytes - 256;
+    na.ready = true;
+  }
+  // the wait bound set by bandred_set_wait_limit_us applies here too
+  if (g_dev[dev].props) na.st.timeout_ticks = g_dev[dev].timeout_ticks;
+  *out = &na.st;
+  return 0;
 }
 
 }  // namespace br
@@ -1090,6 +1146,20 @@ int bandred_ge2gb_ex(int64_t m, int64_t n, int64_t w, int64_t b, double *A, int6
   if (check_prec(prec)) return -9;
   if (check_opts(opts)) return -10;
   return ge2gb_impl(m, n, w, b, A, lda, tauq, taup, prec, opts, (hipStream_t)stream);
+}
+
+int bandred_sy2sb_noalloc(int64_t n, int64_t w, int64_t b, double *A, int64_t lda, double *tau,
+                          int prec, void *stream) {
+  int rc = check_sy2sb(n, w, b, A, lda, tau);
+  if (rc) return rc;
+  if (check_prec(prec)) return -7;
+  DevState *na = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    rc = noalloc_state(&na);
+  }
+  if (rc) return rc;
+  return sy2sb_impl(n, w, b, A, lda, tau, prec, nullptr, (hipStream_t)stream, na);
 }
 
 int bandred_sy2sb_batched(int64_t count, const int64_t *n, int64_t w, int64_t b, double *const *A,
