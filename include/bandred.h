@@ -124,6 +124,55 @@ BANDRED_API int bandred_ge2gb_ex(int64_t m, int64_t n, int64_t w, int64_t b, dou
                      int64_t lda, double *tauq, double *taup, int prec,
                      const bandred_opts_t *opts, void *stream);
 
+/* General A (m x n, m >= n) to band form with lower AND upper bandwidth w
+ * (Sec. 3.3, eqs. updateB0..updateCD22; the left and right updates of the
+ * trailing block applied at once, eq. gebrd_2k).  Arguments as
+ * bandred_ge2gb_ex: m, n (args 1, 2), w, b (3, 4; 1 <= b <= w), A (5, device,
+ * lda x n), lda (6, >= max(1, m)), tauq, taup (7, 8, device, n entries each),
+ * prec (9), opts (10, may be NULL), stream (11).
+ * On return B(i,j) for -w <= j-i <= w holds the band.  Left reflector c
+ * (c <= m-w-2, c < n) has v[0] = 1 implicit at row c+w, v[1:] in
+ * A(c+w+1:m-1, c) and scalar tauq[c]; right reflector c (c <= n-w-2) has
+ * u[0] = 1 at column c+w, u[1:] in A(c, c+w+1:n-1) and scalar taup[c]; all
+ * other tau entries are 0.  U = H_0 H_1 ..., V = G_0 G_1 ..., B = U^T A V.
+ * With look-ahead the next left and right panels are factored on a second
+ * stream beside the update of the trailing block (Variant V1 when 2b <= w,
+ * V2 otherwise).  Asynchronous and capturable like bandred_ge2gb_ex. */
+BANDRED_API int bandred_ge2gb_lu(int64_t m, int64_t n, int64_t w, int64_t b, double *A,
+                     int64_t lda, double *tauq, double *taup, int prec,
+                     const bandred_opts_t *opts, void *stream);
+
+/* Back-transformation: C := Q C (trans = 0) or Q^T C (trans = 1) with the
+ * orthogonal factor of bandred_sy2sb, Q = H_0 H_1 ... H_{n-w-1} (Sec. 2.1:
+ * the reduction accumulates Q as I + W Y^T panel by panel; eigenvectors of
+ * A are Q times those of B).
+ *   trans       0 or 1                                              (arg 1)
+ *   n, w        as given to the reduction                           (args 2, 3)
+ *   b           block of reflectors applied at once, 1 <= b <= 128;
+ *               any value gives the same Q                          (arg 4)
+ *   A, lda      device, the reduction's output (only the reflectors,
+ *               below the band, are read)                           (args 5, 6)
+ *   tau         device, n - w entries                               (arg 7)
+ *   k           columns of C, >= 0                                  (arg 8)
+ *   C, ldc      device, n x k, ldc >= max(1, n), overwritten        (args 9, 10)
+ *   stream      hipStream_t or NULL                                 (arg 11)
+ * FP64.  Asynchronous; capturable like the _ex calls. */
+BANDRED_API int bandred_sy2sb_apply_q(int trans, int64_t n, int64_t w, int64_t b,
+                          const double *A, int64_t lda, const double *tau, int64_t k,
+                          double *C, int64_t ldc, void *stream);
+
+/* Back-transformation for the general reductions (Sec. 3.1 and 3.3):
+ * side 0: C := U C or U^T C (C is m x k); side 1: C := V C or V^T C (C is
+ * n x k).  form 0: the factors of bandred_ge2gb (upper triangular-band);
+ * form 1: those of bandred_ge2gb_lu (equal bandwidths).  tau is tauq for
+ * side 0 and taup for side 1.  Args: side (1), form (2), trans (3), m, n
+ * (4, 5), w (6), b (7, 1..128), A (8), lda (9), tau (10), k (11), C (12),
+ * ldc (13, >= rows of C), stream (14).  FP64, asynchronous. */
+BANDRED_API int bandred_ge2gb_apply(int side, int form, int trans, int64_t m, int64_t n,
+                        int64_t w, int64_t b, const double *A, int64_t lda,
+                        const double *tau, int64_t k, double *C, int64_t ldc,
+                        void *stream);
+
 /* For callers that cannot allocate device memory: code under HIP stream
  * capture with no earlier eager call, serving loops that must not allocate,
  * harnesses that forbid hipMalloc.  Same reduction and arguments as

@@ -64,6 +64,12 @@ def load(path: str = LIB_PATH):
                                      ctypes.POINTER(Opts), _vp]
     lib.bandred_ge2gb_ex.argtypes = [_i64, _i64, _i64, _i64, _vp, _i64, _vp, _vp, ctypes.c_int,
                                      ctypes.POINTER(Opts), _vp]
+    lib.bandred_ge2gb_lu.argtypes = [_i64, _i64, _i64, _i64, _vp, _i64, _vp, _vp, ctypes.c_int,
+                                     ctypes.POINTER(Opts), _vp]
+    lib.bandred_sy2sb_apply_q.argtypes = [ctypes.c_int, _i64, _i64, _i64, _vp, _i64, _vp, _i64,
+                                          _vp, _i64, _vp]
+    lib.bandred_ge2gb_apply.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64, _i64,
+                                        _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp]
     lib.bandred_sy2sb_noalloc.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, ctypes.c_int, _vp]
     lib.bandred_sy2sb_batched.argtypes = [_i64, ctypes.POINTER(_i64), _i64, _i64,
                                           ctypes.POINTER(_vp), ctypes.POINTER(_i64),
@@ -80,7 +86,8 @@ def load(path: str = LIB_PATH):
     for name in ("bandred_sy2sb", "bandred_ge2gb", "bandred_sy2sb_ex", "bandred_ge2gb_ex",
                  "bandred_sy2sb_batched", "bandred_sy2sb_noalloc", "bandred_profile_enable",
                  "bandred_profile_read",
-                 "bandred_status", "bandred_set_wait_limit_us", "bandred_release"):
+                 "bandred_status", "bandred_set_wait_limit_us", "bandred_release",
+                 "bandred_ge2gb_lu", "bandred_sy2sb_apply_q", "bandred_ge2gb_apply"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -114,6 +121,21 @@ def bandred_sy2sb_ex(n, w, b, A, lda, tau, prec=FP64, opts=None, stream=None) ->
 def bandred_ge2gb_ex(m, n, w, b, A, lda, tauq, taup, prec=FP64, opts=None, stream=None) -> int:
     return load().bandred_ge2gb_ex(m, n, w, b, A, lda, tauq, taup, prec,
                                    ctypes.byref(opts) if opts is not None else None, stream)
+
+
+def bandred_ge2gb_lu(m, n, w, b, A, lda, tauq, taup, prec=FP64, opts=None, stream=None) -> int:
+    return load().bandred_ge2gb_lu(m, n, w, b, A, lda, tauq, taup, prec,
+                                   ctypes.byref(opts) if opts is not None else None, stream)
+
+
+def bandred_sy2sb_apply_q(trans, n, w, b, A, lda, tau, k, C, ldc, stream=None) -> int:
+    return load().bandred_sy2sb_apply_q(trans, n, w, b, A, lda, tau, k, C, ldc, stream)
+
+
+def bandred_ge2gb_apply(side, form, trans, m, n, w, b, A, lda, tau, k, C, ldc,
+                        stream=None) -> int:
+    return load().bandred_ge2gb_apply(side, form, trans, m, n, w, b, A, lda, tau, k, C, ldc,
+                                      stream)
 
 
 def bandred_sy2sb_noalloc(n, w, b, A, lda, tau, prec=FP64, stream=None) -> int:
@@ -237,6 +259,57 @@ def ge2gb(A, w: int, b: int | None = None, prec="fp64", lookahead: bool = True,
     _check("bandred_ge2gb_ex", rc)
     _check_status("bandred_ge2gb_ex", h, check)
     return tauq[:n], taup[:n]
+
+
+def ge2gb_lu(A, w: int, b: int | None = None, prec="fp64", lookahead: bool = True,
+             panel_rows: int = 0, panel_method: int = 0, stream=None, check: bool = True):
+    """Reduce the column-major CUDA tensor ``A`` (m >= n) to band form with
+    lower and upper bandwidth ``w`` in place; returns (tauq, taup)."""
+    import torch
+
+    m, n = A.shape
+    b = w if b is None else b
+    lda = _colmajor_ld(A, m)
+    tauq = torch.zeros(max(n, 1), dtype=torch.float64, device=A.device)
+    taup = torch.zeros(max(n, 1), dtype=torch.float64, device=A.device)
+    p = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
+    o = Opts(1 if lookahead else 0, int(panel_rows), int(panel_method))
+    h = _stream_handle(stream)
+    rc = bandred_ge2gb_lu(m, n, w, b, A.data_ptr(), lda, tauq.data_ptr(), taup.data_ptr(), p, o, h)
+    _check("bandred_ge2gb_lu", rc)
+    _check_status("bandred_ge2gb_lu", h, check)
+    return tauq[:n], taup[:n]
+
+
+def sy2sb_apply_q(Aout, tau, w: int, C, trans: bool = False, b: int = 128, stream=None):
+    """C := Q C (or Q^T C) in place for the result (Aout, tau) of ``sy2sb``;
+    C is a column-major CUDA tensor with n rows.  Returns C."""
+    n = Aout.shape[0]
+    lda = _colmajor_ld(Aout, n)
+    ldc = _colmajor_ld(C, n) if C.dim() == 2 else n
+    k = C.shape[1] if C.dim() == 2 else 1
+    rc = bandred_sy2sb_apply_q(1 if trans else 0, n, w, b, Aout.data_ptr(), lda,
+                               tau.data_ptr() if tau.numel() else None, k, C.data_ptr(), ldc,
+                               _stream_handle(stream))
+    _check("bandred_sy2sb_apply_q", rc)
+    return C
+
+
+def ge2gb_apply(Aout, tau, w: int, C, side: str = "u", equal_band: bool = False,
+                trans: bool = False, b: int = 128, stream=None):
+    """C := U C / U^T C (side 'u', tau = tauq) or V C / V^T C (side 'v',
+    tau = taup) in place for the result of ``ge2gb`` or ``ge2gb_lu``."""
+    m, n = Aout.shape
+    lda = _colmajor_ld(Aout, m)
+    rows = m if side == "u" else n
+    ldc = _colmajor_ld(C, rows) if C.dim() == 2 else rows
+    k = C.shape[1] if C.dim() == 2 else 1
+    rc = bandred_ge2gb_apply(0 if side == "u" else 1, 1 if equal_band else 0, 1 if trans else 0,
+                             m, n, w, b, Aout.data_ptr(), lda,
+                             tau.data_ptr() if tau.numel() else None, k, C.data_ptr(), ldc,
+                             _stream_handle(stream))
+    _check("bandred_ge2gb_apply", rc)
+    return C
 
 
 def sy2sb_batched(mats, w: int, b: int | None = None, prec="fp64", stream=None,

@@ -894,6 +894,311 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
 }
 
 // ---------------------------------------------------------------------------
+// GE2GB to the band form with equal lower and upper bandwidth (Sec. 3.3).
+// Per block c (left panel width pbl, right panel width pbr):
+//   1. left QR of B0 = A[c+w:m, c:c+pbl], Wtl = Vl Tl           (eq. updateB0)
+//      right LQ of C0 = A[c:c+pbr, c+w:n], Wtr = Vr Tr          (eq. updateC0)
+//      (independent: their reflectors touch disjoint rows and columns)
+//   2. B1 = A[c+w:m, c+pbl:c+w] -= Vl (Wtl^T B1)                  (eq. updateBD)
+//      C1 = A[c+pbr:c+w, c+w:n] -= (C1 Wtr) Vr^T                  (eq. updateCD2)
+//   3. D = A[c+w:m, c+w:n], both sides at once (eq. gebrd_2k):
+//      ZL = D^T Wtl, ZR = D Wtr, X = ZR - Vl (ZL^T Wtr),
+//      D -= [X, Vl] [Vr, ZL]^T
+// The paper's Q_L = I + W_L Y_L^T is I - Vl Tl Vl^T here (Y = V, W = -V T),
+// so its X and Z_L carry the opposite sign.
+// Look-ahead: when the next panels lie in B1 and C1 (Variant V1, 2b <= w)
+// they are factored on the second stream right after step 2, beside the whole
+// of step 3; otherwise (Variant V2) the parts of D that the next panels need
+// (D11, D21 and D12 of eq. partD) are updated first and the rest (D22)
+// beside the next panels.
+// ---------------------------------------------------------------------------
+static int ge2gb_lu_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double *A,
+                         int64_t lda, double *tauq, double *taup, int prec,
+                         const bandred_opts_t *opts, hipStream_t s) {
+  if (n64 == 0) return 0;
+  if (m64 > (int64_t)1 << 30) return BANDRED_ERR_UNSUPPORTED;
+  const int m = (int)m64, n = (int)n64, w = (int)w64, b = (int)b64;
+  const int panel_rows = opts ? opts->panel_rows : 0;
+  const int method = opts ? opts->panel_method : 0;
+  const bool la = opts ? opts->lookahead != 0 : true;
+  DevState *st = nullptr;
+  int rc = dev_state(&st);
+  if (rc) return rc;
+  // reflectors of length >= 2: left c <= m-w-2, right c <= n-w-2
+  const int nl = std::max(0, std::min(n, m - w - 1));
+  const int nr = std::max(0, n - w - 1);
+  const int npan = (nl + b - 1) / b;
+  if (npan == 0) {  // already banded: every tau is zero
+    rc = launch_fill(tauq, n, 0.0, s); if (rc) return rc;
+    return launch_fill(taup, n, 0.0, s);
+  }
+  const int jlmax = m - w, jrmax = std::max(1, n - w);
+  const size_t part_cap = std::max<size_t>((size_t)8 * std::max(jlmax, jrmax) * b,
+                                           (size_t)256 * b * b);
+  const size_t part_pan = (size_t)(std::max(jlmax, jrmax) / 64 + 2) * b * b;
+  size_t need = 0;
+  need += 2 * round_up((size_t)jlmax * 2 * b * 8, 256);  // XV[2] = [X | Vl]
+  need += 2 * round_up((size_t)jrmax * 2 * b * 8, 256);  // VZ[2] = [Vr | ZL]
+  need += 2 * round_up((size_t)jlmax * b * 8, 256);      // Wtl[2]
+  need += 2 * round_up((size_t)jrmax * b * 8, 256);      // Wtr[2]
+  need += 4 * round_up((size_t)b * b * 8, 256);          // Tl[2], Tr[2]
+  need += 3 * round_up((size_t)b * std::max(b, w) * 8, 256);  // Zb, Yc, P
+  need += round_up(part_cap * 8, 256) + round_up(part_pan * 8, 256);
+  need += PanelWs::bytes(std::max(jlmax, jrmax), b);
+  need += 3 * round_up((size_t)(2 * npan + 2) * 4, 256);
+  need += round_up((size_t)(2 * npan + 2) * 2 * kNbMax * 4, 256);
+  need += 8192;
+  std::lock_guard<std::mutex> lk(g_mu);
+  bool capturing = false;
+  rc = capture_check(s, need, *st, &capturing);
+  if (rc) return rc;
+  rc = ws_reserve(*st, need);
+  if (rc) return rc;
+  Arena ar(st->base);
+  double *XV[2] = {ar.take<double>((size_t)jlmax * 2 * b), ar.take<double>((size_t)jlmax * 2 * b)};
+  double *VZ[2] = {ar.take<double>((size_t)jrmax * 2 * b), ar.take<double>((size_t)jrmax * 2 * b)};
+  double *Wtl[2] = {ar.take<double>((size_t)jlmax * b), ar.take<double>((size_t)jlmax * b)};
+  double *Wtr[2] = {ar.take<double>((size_t)jrmax * b), ar.take<double>((size_t)jrmax * b)};
+  double *Tl[2] = {ar.take<double>((size_t)b * b), ar.take<double>((size_t)b * b)};
+  double *Tr[2] = {ar.take<double>((size_t)b * b), ar.take<double>((size_t)b * b)};
+  const size_t sq = (size_t)b * std::max(b, w);
+  double *Zb = ar.take<double>(sq), *Yc = ar.take<double>(sq), *Pb = ar.take<double>(sq);
+  double *part = ar.take<double>(part_cap);
+  double *partp = ar.take<double>(part_pan);
+  PanelWs pw;
+  pw.carve(ar, std::max(jlmax, jrmax), b);
+  unsigned *counters = ar.take<unsigned>(2 * npan + 2);
+  int *pflags = ar.take<int>(2 * (2 * npan + 2));
+  int *pstruct = ar.take<int>((size_t)(2 * npan + 2) * 2 * kNbMax);
+  Ctx cx{st, s, part, part_cap};
+  hipStream_t ps = la ? st->aux : s;
+  Ctx cxp{st, ps, partp, part_pan};
+
+  if (!capturing) BR_HIP_CHECK(hipStreamWaitEvent(s, st->done, 0));
+  rc = launch_fill_u32(counters, 2 * npan + 2, 0u, s); if (rc) return rc;
+  rc = launch_fill_u32((unsigned *)pflags, 2 * (2 * npan + 2), 0u, s); if (rc) return rc;
+  rc = launch_fill_u32((unsigned *)pstruct, (int64_t)(2 * npan + 2) * 2 * kNbMax, 0u, s);
+  if (rc) return rc;
+  rc = launch_fill_u32((unsigned *)st->flags, 2, 0u, s); if (rc) return rc;
+  g_last_flags[current_dev_index()] = st->flags;
+  rc = launch_fill(tauq, n, 0.0, s); if (rc) return rc;
+  rc = launch_fill(taup, n, 0.0, s); if (rc) return rc;
+
+  auto widths = [&](int c, int *pbl, int *pbr) {
+    *pbl = std::max(0, std::min(b, nl - c));
+    *pbr = std::max(0, std::min(b, nr - c));
+  };
+  // both panels of block `it` and their Wt = V T, on stream q
+  auto panels = [&](int it, Ctx &c_, hipStream_t q) -> int {
+    const int c = it * b, jl = m - c - w, jr = n - c - w;
+    int pbl, pbr;
+    widths(c, &pbl, &pbr);
+    const int k = it & 1;
+    if (pbl > 0) {
+      double *Vl = XV[k] + (int64_t)pbr * jl;  // [X | Vl]: Vl after the pbr columns of X
+      int r = panel_factor(c_, false, A + (c + w) + (int64_t)c * lda, lda, jl, pbl, Vl, jl,
+                           tauq + c, Tl[k], pbl, pw, counters + 2 * it, pflags + 4 * it,
+                           pstruct + (size_t)(2 * it) * 2 * kNbMax, method, panel_rows, q);
+      if (r) return r;
+      r = gemm(c_, C_GEMM_SMALL, A_N, B_N, P_F64, jl, pbl, pbl, Vl, jl, Tl[k], pbl, Wtl[k], jl,
+               1.0, 0.0, q);
+      if (r) return r;
+    }
+    if (pbr > 0) {
+      double *Vr = VZ[k];  // [Vr | ZL]
+      int r = panel_factor(c_, true, A + c + (int64_t)(c + w) * lda, lda, jr, pbr, Vr, jr,
+                           taup + c, Tr[k], pbr, pw, counters + 2 * it + 1, pflags + 4 * it + 2,
+                           pstruct + (size_t)(2 * it + 1) * 2 * kNbMax, method, panel_rows, q);
+      if (r) return r;
+      r = gemm(c_, C_GEMM_SMALL, A_N, B_N, P_F64, jr, pbr, pbr, Vr, jr, Tr[k], pbr, Wtr[k], jr,
+               1.0, 0.0, q);
+      if (r) return r;
+    }
+    return 0;
+  };
+  auto fork = [&](int it) -> int {
+    if (ps != s) {
+      BR_HIP_CHECK(hipEventRecord(st->ev_a, s));
+      BR_HIP_CHECK(hipStreamWaitEvent(ps, st->ev_a, 0));
+    }
+    return panels(it, cxp, ps);
+  };
+  auto join = [&]() -> int {
+    if (ps != s) {
+      BR_HIP_CHECK(hipEventRecord(st->ev_b, ps));
+      BR_HIP_CHECK(hipStreamWaitEvent(s, st->ev_b, 0));
+    }
+    return 0;
+  };
+
+  rc = panels(0, cx, s);
+  if (rc) return rc;
+  for (int it = 0; it < npan; ++it) {
+    const int c = it * b, jl = m - c - w, jr = n - c - w;
+    int pbl, pbr;
+    widths(c, &pbl, &pbr);
+    const int k = it & 1;
+    double *Vl = XV[k] + (int64_t)pbr * jl, *Vr = VZ[k];
+    const bool next = it + 1 < npan;
+    int pbl2 = 0, pbr2 = 0;
+    if (next) widths(c + b, &pbl2, &pbr2);
+    // columns / rows of D that the next panels take (Variant V2 when nonzero)
+    const int aL = next ? std::max(0, std::min(jr, c + b + pbl2 - (c + w))) : 0;
+    const int aR = next ? std::max(0, std::min(jl, c + b + pbr2 - (c + w))) : 0;
+
+    // (2) B1 and C1
+    const int nb1 = std::min(c + w, n) - (c + pbl);
+    if (pbl > 0 && nb1 > 0) {
+      double *B1 = A + (c + w) + (int64_t)(c + pbl) * lda;
+      rc = gemm(cx, C_GEMM_SMALL, A_T, B_N, prec, pbl, nb1, jl, Wtl[k], jl, B1, lda, Zb, pbl,
+                1.0, 0.0, s);
+      if (rc) return rc;
+      rc = gemm(cx, C_GEMM_UPD, A_N, B_N, prec, jl, nb1, pbl, Vl, jl, Zb, pbl, B1, lda, -1.0,
+                1.0, s);
+      if (rc) return rc;
+    }
+    const int mc1 = std::min(c + w, m) - (c + pbr);
+    if (pbr > 0 && mc1 > 0) {
+      double *C1 = A + (c + pbr) + (int64_t)(c + w) * lda;
+      rc = gemm(cx, C_GEMM_SMALL, A_N, B_N, prec, mc1, pbr, jr, C1, lda, Wtr[k], jr, Yc, mc1,
+                1.0, 0.0, s);
+      if (rc) return rc;
+      rc = gemm(cx, C_GEMM_UPD, A_N, B_T, prec, mc1, jr, pbr, Yc, mc1, Vr, jr, C1, lda, -1.0,
+                1.0, s);
+      if (rc) return rc;
+    }
+    const bool v1 = next && aL == 0 && aR == 0;
+    if (v1) {
+      rc = fork(it + 1);
+      if (rc) return rc;
+    }
+    // (3) D, both sides at once
+    if (jr > 0 && jl > 0) {
+      double *D = A + (c + w) + (int64_t)(c + w) * lda;
+      double *ZL = VZ[k] + (int64_t)pbr * jr;
+      double *X = XV[k];
+      if (pbl > 0) {  // ZL = D^T Wtl
+        rc = gemm(cx, C_GEMM_UPD, A_T, B_N, prec, jr, pbl, jl, D, lda, Wtl[k], jl, ZL, jr, 1.0,
+                  0.0, s);
+        if (rc) return rc;
+      }
+      if (pbr > 0) {  // ZR = D Wtr into X's slot; X = ZR - Vl (ZL^T Wtr)
+        rc = gemm(cx, C_GEMM_UPD, A_N, B_N, prec, jl, pbr, jr, D, lda, Wtr[k], jr, X, jl, 1.0,
+                  0.0, s);
+        if (rc) return rc;
+        if (pbl > 0) {
+          rc = gemm(cx, C_GEMM_SMALL, A_T, B_N, P_F64, pbl, pbr, jr, ZL, jr, Wtr[k], jr, Pb, pbl,
+                    1.0, 0.0, s);
+          if (rc) return rc;
+          rc = gemm(cx, C_GEMM_SMALL, A_N, B_N, P_F64, jl, pbr, pbl, Vl, jl, Pb, pbl, X, jl,
+                    -1.0, 1.0, s);
+          if (rc) return rc;
+        }
+      }
+      // D -= [X | Vl] [Vr | ZL]^T over the rank pbr + pbl
+      const int K = pbr + pbl;
+      auto upd = [&](int r0, int r1, int c0, int c1, bool chunked) -> int {
+        if (r1 <= r0 || c1 <= c0) return 0;
+        if (chunked)
+          return gemm_chunked(cx, C_GEMM_UPD, A_N, B_T, prec, r1 - r0, c1 - c0, K, X + r0, jl,
+                              VZ[k] + c0, jr, D + r0 + (int64_t)c0 * lda, lda, -1.0, 1.0, s);
+        return gemm(cx, C_GEMM_UPD, A_N, B_T, prec, r1 - r0, c1 - c0, K, X + r0, jl, VZ[k] + c0,
+                    jr, D + r0 + (int64_t)c0 * lda, lda, -1.0, 1.0, s);
+      };
+      if (next && !v1 && ps != s) {
+        rc = upd(0, jl, 0, aL, false);   // D11 and D21: the next left panel's columns
+        if (rc) return rc;
+        rc = upd(0, aR, aL, jr, false);  // D12: the next right panel's rows
+        if (rc) return rc;
+        rc = fork(it + 1);
+        if (rc) return rc;
+        rc = upd(aR, jl, aL, jr, true);  // D22 beside the next panels
+        if (rc) return rc;
+      } else {
+        rc = upd(0, jl, 0, jr, v1 && ps != s);
+        if (rc) return rc;
+      }
+    }
+    if (next) {
+      if (v1 || (jr > 0 && jl > 0 && ps != s)) {
+        rc = join();
+      } else {
+        rc = panels(it + 1, cx, s);  // serial order (or no D left to overlap)
+      }
+      if (rc) return rc;
+    }
+  }
+  if (!capturing) BR_HIP_CHECK(hipEventRecord(st->done, s));
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Back-transformation: C := Q C or Q^T C for the stored reflectors of a
+// reduction, Q = H_0 H_1 ... H_{nrefl-1} with reflector i acting on indices
+// i+off .. len-1 (its vector in column i, or row i for right reflectors).
+// Blocks of b reflectors are applied as I - V T V^T (Q^T: I - V T^T V^T),
+// the compact WY form in which the reductions accumulate Q (Sec. 2.1,
+// Q = I + W Y^T): V copied out of the storage, T from V^T V and tau (the
+// LARFT recurrence), then C -= V (op(T) (V^T C)).
+// ---------------------------------------------------------------------------
+static int apply_impl(int rowstore, int64_t off, int64_t nrefl, int64_t len, const double *A,
+                      int64_t lda, const double *tau, int trans, int64_t k64, double *C,
+                      int64_t ldc, int b, hipStream_t s) {
+  if (nrefl <= 0 || k64 <= 0) return 0;
+  if (len > ((int64_t)1 << 30) || k64 > ((int64_t)1 << 30)) return BANDRED_ERR_UNSUPPORTED;
+  const int k = (int)k64;
+  DevState *st = nullptr;
+  int rc = dev_state(&st);
+  if (rc) return rc;
+  const int jmax = (int)(len - off);
+  const size_t part_cap = std::max<size_t>((size_t)8 * b * std::max(k, b), (size_t)256 * b * b);
+  size_t need = round_up((size_t)jmax * b * 8, 256) + 2 * round_up((size_t)b * b * 8, 256) +
+                2 * round_up((size_t)b * k * 8, 256) + round_up(part_cap * 8, 256) + 4096;
+  std::lock_guard<std::mutex> lk(g_mu);
+  bool capturing = false;
+  rc = capture_check(s, need, *st, &capturing);
+  if (rc) return rc;
+  rc = ws_reserve(*st, need);
+  if (rc) return rc;
+  Arena ar(st->base);
+  double *V = ar.take<double>((size_t)jmax * b);
+  double *S = ar.take<double>((size_t)b * b), *T = ar.take<double>((size_t)b * b);
+  double *Z = ar.take<double>((size_t)b * k), *Z2 = ar.take<double>((size_t)b * k);
+  double *part = ar.take<double>(part_cap);
+  Ctx cx{st, s, part, part_cap};
+  if (!capturing) BR_HIP_CHECK(hipStreamWaitEvent(s, st->done, 0));
+  rc = launch_fill_u32((unsigned *)st->flags, 2, 0u, s); if (rc) return rc;
+  g_last_flags[current_dev_index()] = st->flags;
+  const int nblk = (int)((nrefl + b - 1) / b);
+  for (int q = 0; q < nblk; ++q) {
+    const int bi = trans ? q : nblk - 1 - q;  // Q C: last block first
+    const int64_t i0 = (int64_t)bi * b;
+    const int pb = (int)std::min<int64_t>(b, nrefl - i0);
+    const int64_t r0 = i0 + off;
+    const int j = (int)(len - r0);
+    double *Cr = C + r0;
+    rc = launch_extract_v(A, lda, rowstore, r0, i0, pb, j, V, j, s);
+    if (rc) return rc;
+    rc = gemm(cx, C_GEMM_SMALL, A_T, B_N, P_F64, pb, pb, j, V, j, V, j, S, pb, 1.0, 0.0, s);
+    if (rc) return rc;
+    {
+      ProfScope p2(C_LARFT, 0.0, s);
+      rc = launch_larft(S, pb, tau + i0, pb, T, pb, s);
+      if (rc) return rc;
+    }
+    rc = gemm(cx, C_GEMM_UPD, A_T, B_N, P_F64, pb, k, j, V, j, Cr, ldc, Z, pb, 1.0, 0.0, s);
+    if (rc) return rc;
+    rc = gemm(cx, C_GEMM_SMALL, trans ? A_T : A_N, B_N, P_F64, pb, k, pb, T, pb, Z, pb, Z2, pb,
+              1.0, 0.0, s);
+    if (rc) return rc;
+    rc = gemm(cx, C_GEMM_UPD, A_N, B_N, P_F64, j, k, pb, V, j, Z2, pb, Cr, ldc, -1.0, 1.0, s);
+    if (rc) return rc;
+  }
+  if (!capturing) BR_HIP_CHECK(hipEventRecord(st->done, s));
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
 // Batched SY2SB: one persistent launch over a table of matrices sorted by
 // decreasing order; matrices the kernel cannot hold (b > 16 or n - w > 1024)
 // go through the single-matrix path on the same stream afterwards.
@@ -1146,6 +1451,63 @@ int bandred_ge2gb_ex(int64_t m, int64_t n, int64_t w, int64_t b, double *A, int6
   if (check_prec(prec)) return -9;
   if (check_opts(opts)) return -10;
   return ge2gb_impl(m, n, w, b, A, lda, tauq, taup, prec, opts, (hipStream_t)stream);
+}
+
+int bandred_ge2gb_lu(int64_t m, int64_t n, int64_t w, int64_t b, double *A, int64_t lda,
+                     double *tauq, double *taup, int prec, const bandred_opts_t *opts,
+                     void *stream) {
+  int rc = check_ge2gb(m, n, w, b, A, lda, tauq, taup);
+  if (rc) return rc;
+  if (check_prec(prec)) return -9;
+  if (check_opts(opts)) return -10;
+  return ge2gb_lu_impl(m, n, w, b, A, lda, tauq, taup, prec, opts, (hipStream_t)stream);
+}
+
+int bandred_sy2sb_apply_q(int trans, int64_t n, int64_t w, int64_t b, const double *A,
+                          int64_t lda, const double *tau, int64_t k, double *C, int64_t ldc,
+                          void *stream) {
+  if (trans != 0 && trans != 1) return -1;
+  if (n < 0) return -2;
+  if (w < 1) return -3;
+  if (b < 1 || b > kNbMax) return -4;
+  const int64_t nrefl = n > w ? n - w : 0;
+  if (nrefl > 0 && A == nullptr) return -5;
+  if (lda < (n > 1 ? n : 1)) return -6;
+  if (nrefl > 0 && tau == nullptr) return -7;
+  if (k < 0) return -8;
+  if (k > 0 && n > 0 && C == nullptr) return -9;
+  if (ldc < (n > 1 ? n : 1)) return -10;
+  return apply_impl(0, w, nrefl, n, A, lda, tau, trans, k, C, ldc, (int)b, (hipStream_t)stream);
+}
+
+int bandred_ge2gb_apply(int side, int form, int trans, int64_t m, int64_t n, int64_t w, int64_t b,
+                        const double *A, int64_t lda, const double *tau, int64_t k, double *C,
+                        int64_t ldc, void *stream) {
+  if (side != 0 && side != 1) return -1;
+  if (form != 0 && form != 1) return -2;
+  if (trans != 0 && trans != 1) return -3;
+  if (m < 0) return -4;
+  if (n < 0 || n > m) return (n < 0) ? -5 : -4;
+  if (w < 1) return -6;
+  if (b < 1 || b > kNbMax) return -7;
+  int64_t off, nrefl, len;
+  if (side == 0) {  // U: column storage, m x k
+    off = form ? w : 0;
+    nrefl = form ? std::max<int64_t>(0, std::min<int64_t>(n, m - w)) : n;
+    len = m;
+  } else {          // V: row storage from column w on, n x k
+    off = w;
+    nrefl = std::max<int64_t>(0, n - w);
+    len = n;
+  }
+  if (nrefl > 0 && A == nullptr) return -8;
+  if (lda < (m > 1 ? m : 1)) return -9;
+  if (nrefl > 0 && tau == nullptr) return -10;
+  if (k < 0) return -11;
+  if (k > 0 && len > 0 && C == nullptr) return -12;
+  if (ldc < (len > 1 ? len : 1)) return -13;
+  return apply_impl(side, off, nrefl, len, A, lda, tau, trans, k, C, ldc, (int)b,
+                    (hipStream_t)stream);
 }
 
 int bandred_sy2sb_noalloc(int64_t n, int64_t w, int64_t b, double *A, int64_t lda, double *tau,

@@ -113,6 +113,8 @@ int launch_panel_structure(const double *P, int64_t ldp, int rowmajor, int m, in
 int launch_panel_finalize(double *P, int64_t ldp, int rowmajor, int m, int b, const double *V,
                           int64_t ldv, const double *Rh0, const double *sgn, const int *flag,
                           hipStream_t s);
+int launch_extract_v(const double *A, int64_t lda, int rowstore, int64_t r0, int64_t i0, int pb,
+                     int j, double *V, int64_t ldv, hipStream_t s);
 constexpr int kPackedMax = kNbMax * (kNbMax + 1) / 2;
 int launch_fill(double *p, int64_t count, double v, hipStream_t s);
 int launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t s);
