@@ -267,11 +267,14 @@ static int gemm(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int 
   d.lds_pad = lds_pad;
   d.abort = cx.st->flags + 1;
   d.prio = (cls == C_PANEL || cls == C_GEMM_SMALL) ? 1 : 0;
-  const int bm = (M <= 64 && N <= 64) ? 64 : 128;
-  const int tiles = ((M + bm - 1) / bm) * ((N + bm - 1) / bm);
+  int tm = 128, tn = 128;
+  gemm_tile_shape(E_AXPBY, M, N, 0, &tm, &tn);
+  if (tm == 64 && tn == 64 && (M > 64 || N > 64)) tm = tn = 128;  // (may still take 64 x 64 below)
+  const int tiles = ((M + tm - 1) / tm) * ((N + tn - 1) / tn);
   // workgroups resident at once: two per CU for the 128 x 128 tiles (VGPRs
-  // and LDS), four for the 64 x 64 ones
-  const int slots = (bm == 128 ? 2 : 4) * cx.st->num_cu;
+  // and LDS), three for 128 x 64 and 64 x 128 (LDS), four for 64 x 64
+  const int per_cu = (tm == 128 && tn == 128) ? 2 : (tm == 64 && tn == 64) ? 4 : 3;
+  const int slots = per_cu * cx.st->num_cu;
   // k-chunk granularity: the panel's Gram products (beside the running update
   // more, shorter workgroups finish sooner) take chunks of 128 rows, or of 64
   // for outputs of one 64 x 64 tile (b <= 64), which need more splits to fill
@@ -302,7 +305,7 @@ static int gemm(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int 
   if (ks == 1) {
     // too few 128 x 128 tiles to occupy every CU and no k split: 64 x 64
     // tiles give four times the workgroups
-    if (bm == 128 && tiles < cx.st->num_cu) d.tile64 = 1;
+    if (tm == 128 && tn == 128 && tiles < cx.st->num_cu) d.tile64 = 1;
     d.kchunk = (int)round_up(K, kBK);
     ProfScope ps(cls, flops, s);
     return launch_gemm(opa, opb, E_AXPBY, prec, d, 1, s);

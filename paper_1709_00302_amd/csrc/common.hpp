@@ -96,6 +96,8 @@ int hip_fail(hipError_t e, const char *what);
 // host-side launchers (defined in gemm.hip / panel.hip)
 int launch_gemm(int opa, int opb, int epi, int prec, const GemmDesc &d, int ksplit,
                 hipStream_t s);
+// output tile of launch_gemm for an M x N product (tile64: force 64 x 64)
+int gemm_tile_shape(int epi, int M, int N, int tile64, int *tm, int *tn);
 int launch_reduce_partials(const double *part, int ksplit, int M, int N, double alpha,
                            double *C, int64_t ldc, double beta, hipStream_t s,
                            const int *gate = nullptr, int gate_val = 0,

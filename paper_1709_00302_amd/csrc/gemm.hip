@@ -500,20 +500,56 @@ static int dispatch_ops(int opa, int opb, int epi, const GemmDesc &d, int ksplit
   return BANDRED_ERR_UNSUPPORTED;
 }
 
-int launch_gemm(int opa, int opb, int epi, int prec, const GemmDesc &d, int ksplit,
-                hipStream_t s) {
+// Rectangular tiles for products with one narrow output side (no SYR2K).
+template <int BM, int BN, int PREC>
+static int dispatch_rect(int opa, int opb, int epi, const GemmDesc &d, int ksplit, hipStream_t s) {
+#define BR_CASE(OA, OB, EP) \
+  if (opa == OA && opb == OB && epi == EP) return launch_t<BM, BN, OA, OB, EP, PREC>(d, ksplit, s);
+  BR_CASE(A_SYM, B_N, E_PART)
+  BR_CASE(A_SYM, B_N, E_AXPBY)
+  BR_CASE(A_N, B_N, E_AXPBY)
+  BR_CASE(A_N, B_N, E_PART)
+  BR_CASE(A_T, B_N, E_AXPBY)
+  BR_CASE(A_T, B_N, E_PART)
+  BR_CASE(A_N, B_T, E_AXPBY)
+  BR_CASE(A_N, B_T, E_PART)
+#undef BR_CASE
+  return BANDRED_ERR_UNSUPPORTED;
+}
+
+int gemm_tile_shape(int epi, int M, int N, int tile64, int *tm, int *tn) {
   // 64 x 64 tiles for outputs up to 128 x 128 (the b x b products and Gram
   // matrices), so that such products still spread over several workgroups,
   // and when the caller asks for them (products with fewer 128 x 128 tiles
-  // than CUs and no k split)
-  const bool small = d.tile64 || (d.M <= 128 && (epi == E_SYR2K ? (d.c1 - d.c0) : d.N) <= 128);
+  // than CUs and no k split); 128 x 64 (64 x 128) when the output has at most
+  // 64 columns (rows), so that no wave computes a block of zero columns
+  if (tile64 || (M <= 128 && N <= 128)) {
+    *tm = 64; *tn = 64;
+  } else if (epi != E_SYR2K && N <= 64) {
+    *tm = 128; *tn = 64;
+  } else if (epi != E_SYR2K && M <= 64) {
+    *tm = 64; *tn = 128;
+  } else {
+    *tm = 128; *tn = 128;
+  }
+  return 0;
+}
+
+int launch_gemm(int opa, int opb, int epi, int prec, const GemmDesc &d, int ksplit,
+                hipStream_t s) {
+  int tm = 128, tn = 128;
+  gemm_tile_shape(epi, d.M, epi == E_SYR2K ? (d.c1 - d.c0) : d.N, d.tile64, &tm, &tn);
   int rc;
   if (prec == P_F64) {
-    rc = small ? dispatch_ops<64, 64, P_F64>(opa, opb, epi, d, ksplit, s)
-               : dispatch_ops<128, 128, P_F64>(opa, opb, epi, d, ksplit, s);
+    rc = (tm == 64 && tn == 64) ? dispatch_ops<64, 64, P_F64>(opa, opb, epi, d, ksplit, s)
+         : (tn == 64)           ? dispatch_rect<128, 64, P_F64>(opa, opb, epi, d, ksplit, s)
+         : (tm == 64)           ? dispatch_rect<64, 128, P_F64>(opa, opb, epi, d, ksplit, s)
+                                : dispatch_ops<128, 128, P_F64>(opa, opb, epi, d, ksplit, s);
   } else if (prec == P_F32) {
-    rc = small ? dispatch_ops<64, 64, P_F32>(opa, opb, epi, d, ksplit, s)
-               : dispatch_ops<128, 128, P_F32>(opa, opb, epi, d, ksplit, s);
+    rc = (tm == 64 && tn == 64) ? dispatch_ops<64, 64, P_F32>(opa, opb, epi, d, ksplit, s)
+         : (tn == 64)           ? dispatch_rect<128, 64, P_F32>(opa, opb, epi, d, ksplit, s)
+         : (tm == 64)           ? dispatch_rect<64, 128, P_F32>(opa, opb, epi, d, ksplit, s)
+                                : dispatch_ops<128, 128, P_F32>(opa, opb, epi, d, ksplit, s);
   } else {
     rc = dispatch_ops<64, 64, P_SPLIT>(opa, opb, epi, d, ksplit, s);
   }

@@ -44,8 +44,11 @@ def _graph(run, restore):
     return out, g
 
 
-def test_sy2sb_full_size_graph_replay(bandred, orc):
-    name = "sy2sb_n16384_w128"
+# the headline workload, the n = 8192, w = b = 64 one, and the Variant V1
+# workload (w = 256, b = 128: the next panel lies in A1 and is factored beside
+# the whole trailing update)
+@pytest.mark.parametrize("name", ["sy2sb_n16384_w128", "sy2sb_n8192_w64", "sy2sb_n16384_w256"])
+def test_sy2sb_full_size_graph_replay(bandred, orc, name):
     print(f"case {name}: building the input on the GPU", flush=True)
     p = inputs.make_on_device(name, device="cuda")
     A0, n, w, b = p["A"], p["n"], p["w"], p["b"]
@@ -87,8 +90,8 @@ def test_sy2sb_full_size_graph_replay(bandred, orc):
     assert db <= tol * bmax and dv <= tol and dt <= tol, (db, dv, dt)
 
 
-def test_ge2gb_full_size_graph_replay(bandred, orc):
-    name = "ge2gb_24576x12288_w128"
+@pytest.mark.parametrize("name", ["ge2gb_24576x12288_w128", "ge2gb_8192_w64"])
+def test_ge2gb_full_size_graph_replay(bandred, orc, name):
     print(f"case {name}: building the input on the GPU", flush=True)
     p = inputs.make_on_device(name, device="cuda")
     A0, m, n, w, b = p["A"], p["m"], p["n"], p["w"], p["b"]
