@@ -74,7 +74,8 @@ typedef struct {
  * (Sec. 2.1; look-ahead variants of Sec. 2.2).
  *   n    order of A, n >= 0                                      (arg 1)
  *   w    bandwidth, w >= 1                                       (arg 2)
- *   b    block size, 1 <= b <= w                                 (arg 3)
+ *   b    block size, 1 <= b <= w (bandred_sy2sb_ex: 0 = tuned, see
+ *        bandred_tune)                                           (arg 3)
  *   A    device, lda x n; only the LOWER triangle is read and written; the
  *        strict upper triangle is never referenced                (arg 4)
  *   lda  >= max(1, n)                                            (arg 5)
@@ -212,6 +213,31 @@ BANDRED_API int bandred_sy2sb_noalloc(int64_t n, int64_t w, int64_t b, double *A
 BANDRED_API int bandred_sy2sb_batched(int64_t count, const int64_t *n, int64_t w, int64_t b,
                           double *const *A, const int64_t *lda,
                           double *const *tau, int prec, void *stream);
+
+/* Block-size autotuner (Sec. 4.2: the best block size depends on n and w,
+ * and the paper tunes it per problem in steps of 16).  The reduction's result
+ * does not depend on b (up to rounding), so b is picked by timing the
+ * reduction of a synthetic matrix of the same shape for every candidate b in
+ * {16, 32, ..., min(w, 128)} (b = w when w < 16) on the current device.
+ *   kind      0: bandred_sy2sb_ex (m ignored), 1: bandred_ge2gb_ex,
+ *             2: bandred_ge2gb_lu                                    (arg 1)
+ *   m, n, w   problem shape as in those calls                        (args 2-4)
+ *   prec      precision form                                         (arg 5)
+ *   force     nonzero: measure again even if cached                  (arg 6)
+ *   b_out     HOST, receives the chosen b                            (arg 7)
+ *   ms_out    HOST, may be NULL: up to cap {b, milliseconds} pairs of the
+ *             candidates measured by this call (zeros when it used the
+ *             cache)                                                 (args 8, 9)
+ * The choice is cached per device in memory and, if the environment variable
+ * BANDRED_TUNE_CACHE names a file, appended to it as one JSON object per line
+ * ({"kind": ..., "m": ..., "n": ..., "w": ..., "prec": ..., "b": ..., "ms":
+ * {...}}), from which later processes read it back.  Synchronous; allocates
+ * the trial matrix; must not be called under stream capture.  The _ex calls
+ * and bandred_ge2gb_lu accept b = 0 to mean "the tuned b" (tuned on first use
+ * outside capture; under capture only a cached choice is used, else
+ * BANDRED_ERR_UNSUPPORTED). */
+BANDRED_API int bandred_tune(int kind, int64_t m, int64_t n, int64_t w, int prec, int force,
+                 int64_t *b_out, double *ms_out, int cap);
 
 /* Static description of a status code. */
 BANDRED_API const char *bandred_status_string(int status);

@@ -70,6 +70,9 @@ def load(path: str = LIB_PATH):
                                           _vp, _i64, _vp]
     lib.bandred_ge2gb_apply.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64, _i64,
                                         _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp]
+    lib.bandred_tune.argtypes = [ctypes.c_int, _i64, _i64, _i64, ctypes.c_int, ctypes.c_int,
+                                 ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
+                                 ctypes.c_int]
     lib.bandred_sy2sb_noalloc.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, ctypes.c_int, _vp]
     lib.bandred_sy2sb_batched.argtypes = [_i64, ctypes.POINTER(_i64), _i64, _i64,
                                           ctypes.POINTER(_vp), ctypes.POINTER(_i64),
@@ -87,7 +90,8 @@ def load(path: str = LIB_PATH):
                  "bandred_sy2sb_batched", "bandred_sy2sb_noalloc", "bandred_profile_enable",
                  "bandred_profile_read",
                  "bandred_status", "bandred_set_wait_limit_us", "bandred_release",
-                 "bandred_ge2gb_lu", "bandred_sy2sb_apply_q", "bandred_ge2gb_apply"):
+                 "bandred_ge2gb_lu", "bandred_sy2sb_apply_q", "bandred_ge2gb_apply",
+                 "bandred_tune"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -136,6 +140,17 @@ def bandred_ge2gb_apply(side, form, trans, m, n, w, b, A, lda, tau, k, C, ldc,
                         stream=None) -> int:
     return load().bandred_ge2gb_apply(side, form, trans, m, n, w, b, A, lda, tau, k, C, ldc,
                                       stream)
+
+
+def bandred_tune(kind, m, n, w, prec=FP64, force=False):
+    """Tuned block size: returns (b, {b: ms} of the candidates measured now)."""
+    b = _i64(0)
+    buf = (ctypes.c_double * 32)()
+    rc = load().bandred_tune(int(kind), m, n, w, int(prec), 1 if force else 0, ctypes.byref(b),
+                             buf, 16)
+    _check("bandred_tune", rc)
+    ms = {int(buf[2 * i]): buf[2 * i + 1] for i in range(16) if buf[2 * i] > 0}
+    return int(b.value), ms
 
 
 def bandred_sy2sb_noalloc(n, w, b, A, lda, tau, prec=FP64, stream=None) -> int:

@@ -674,19 +674,30 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
     };
 
     // (3) A1 = A[r:n, c+pb : r] -= V T^T (V^T A1) = V (Wt^T A1)   (eq. updateA1)
+    // Variant V1 (the next panel lies inside A1, 2b <= w): A1 is split as in
+    // eq. partitionV1 into A1^L, the next panel's columns, which is updated
+    // before the next panel is forked, and A1^R, updated on the main stream
+    // beside that panel together with A2.
     const int a1w = w - pb;
-    if (a1w > 0) {
-      double *A1 = A + r + (int64_t)(c + pb) * lda;
-      rc = gemm(cxm, C_GEMM_SMALL, A_T, B_N, P_F64, pb, a1w, j, Wt, j, A1, lda, Zb, pb, 1.0, 0.0, s);
-      if (rc) return rc;
-      rc = gemm(cxm, C_GEMM_UPD, A_N, B_N, prec, j, a1w, pb, V, j, Zb, pb, A1, lda, -1.0, 1.0, s);
-      if (rc) return rc;
-    }
-    // Variant V1 (the next panel lies inside A1): fork right away
-    if (a2L == 0) {
+    auto update_a1 = [&](int q0, int q1) -> int {  // A1 columns [q0, q1)
+      if (q1 <= q0) return 0;
+      double *A1 = A + r + (int64_t)(c + pb + q0) * lda;
+      int e = gemm(cxm, C_GEMM_SMALL, A_T, B_N, P_F64, pb, q1 - q0, j, Wt, j, A1, lda, Zb, pb,
+                   1.0, 0.0, s);
+      if (e) return e;
+      return gemm(cxm, C_GEMM_UPD, A_N, B_N, prec, j, q1 - q0, pb, V, j, Zb, pb, A1, lda, -1.0,
+                  1.0, s);
+    };
+    const bool v1 = has_next && a2L == 0;
+    const int a1L = v1 ? std::min(a1w, cn + pbn - (c + pb)) : a1w;  // A1^L: A1 columns [0, a1L)
+    rc = update_a1(0, a1L);
+    if (rc) return rc;
+    if (v1) {
       rc = fork_next();
       if (rc) return rc;
     }
+    rc = update_a1(a1L, a1w);  // A1^R (empty in Variant V2)
+    if (rc) return rc;
     // (4) X = A2 Wt (SYMM) into W's slot; M = Wt^T X; W = X - 1/2 V M
     rc = gemm(cxm, C_SYMM, A_SYM, B_N, prec, j, pb, j, A2, lda, Wt, j, W, j, 1.0, 0.0, s);
     if (rc) return rc;
@@ -1439,30 +1450,48 @@ int bandred_ge2gb(int64_t m, int64_t n, int64_t w, int64_t b, double *A, int64_t
 
 int bandred_sy2sb_ex(int64_t n, int64_t w, int64_t b, double *A, int64_t lda, double *tau,
                      int prec, const bandred_opts_t *opts, void *stream) {
-  int rc = check_sy2sb(n, w, b, A, lda, tau);
+  int rc = check_sy2sb(n, w, b == 0 ? std::min<int64_t>(w, kNbMax) : b, A, lda, tau);
   if (rc) return rc;
   if (check_prec(prec)) return -7;
   if (check_opts(opts)) return -8;
+  if (b == 0) {  // the autotuner's block size
+    int bt = 0;
+    rc = tune_pick(0, n, n, w, prec, (hipStream_t)stream, &bt);
+    if (rc) return rc;
+    b = bt;
+  }
   return sy2sb_impl(n, w, b, A, lda, tau, prec, opts, (hipStream_t)stream);
 }
 
 int bandred_ge2gb_ex(int64_t m, int64_t n, int64_t w, int64_t b, double *A, int64_t lda,
                      double *tauq, double *taup, int prec, const bandred_opts_t *opts,
                      void *stream) {
-  int rc = check_ge2gb(m, n, w, b, A, lda, tauq, taup);
+  int rc = check_ge2gb(m, n, w, b == 0 ? std::min<int64_t>(w, kNbMax) : b, A, lda, tauq, taup);
   if (rc) return rc;
   if (check_prec(prec)) return -9;
   if (check_opts(opts)) return -10;
+  if (b == 0) {
+    int bt = 0;
+    rc = tune_pick(1, m, n, w, prec, (hipStream_t)stream, &bt);
+    if (rc) return rc;
+    b = bt;
+  }
   return ge2gb_impl(m, n, w, b, A, lda, tauq, taup, prec, opts, (hipStream_t)stream);
 }
 
 int bandred_ge2gb_lu(int64_t m, int64_t n, int64_t w, int64_t b, double *A, int64_t lda,
                      double *tauq, double *taup, int prec, const bandred_opts_t *opts,
                      void *stream) {
-  int rc = check_ge2gb(m, n, w, b, A, lda, tauq, taup);
+  int rc = check_ge2gb(m, n, w, b == 0 ? std::min<int64_t>(w, kNbMax) : b, A, lda, tauq, taup);
   if (rc) return rc;
   if (check_prec(prec)) return -9;
   if (check_opts(opts)) return -10;
+  if (b == 0) {
+    int bt = 0;
+    rc = tune_pick(2, m, n, w, prec, (hipStream_t)stream, &bt);
+    if (rc) return rc;
+    b = bt;
+  }
   return ge2gb_lu_impl(m, n, w, b, A, lda, tauq, taup, prec, opts, (hipStream_t)stream);
 }
 

@@ -117,6 +117,10 @@ int launch_panel_finalize(double *P, int64_t ldp, int rowmajor, int m, int b, co
                           hipStream_t s);
 int launch_extract_v(const double *A, int64_t lda, int rowstore, int64_t r0, int64_t i0, int pb,
                      int j, double *V, int64_t ldv, hipStream_t s);
+// block size picked by the autotuner (tune.hip) for a call with b = 0
+// (kind 0: sy2sb, 1: ge2gb, 2: ge2gb_lu)
+int tune_pick(int kind, int64_t m, int64_t n, int64_t w, int prec, hipStream_t s, int *b_out);
+int tune_lookup(int kind, int64_t m, int64_t n, int64_t w, int prec);
 constexpr int kPackedMax = kNbMax * (kNbMax + 1) / 2;
 int launch_fill(double *p, int64_t count, double v, hipStream_t s);
 int launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t s);

@@ -144,10 +144,14 @@ def test_numerically_dependent_columns(bandred):
     assert err["backward"] <= 1e-14 * n and err["orth"] <= 1e-14 * n, err
 
 
-def test_lookahead_is_bit_identical_to_serial(bandred):
-    A = inputs.sym_normal(900, 21)
-    a1, t1, _ = _run(bandred, A, 64, 64, lookahead=True)
-    a2, t2, _ = _run(bandred, A, 64, 64, lookahead=False)
+# Variant V2 (2b > w) and V1 (2b <= w: A1^L before the fork, A1^R beside the
+# next panel, eq. partitionV1)
+@pytest.mark.parametrize("n,w,b", [(900, 64, 64), (900, 128, 64), (700, 96, 32), (1100, 256, 128)])
+def test_lookahead_is_bit_identical_to_serial(bandred, n, w, b):
+    print(f"case sy2sb lookahead n={n} w={w} b={b}", flush=True)
+    A = inputs.sym_normal(n, 21)
+    a1, t1, _ = _run(bandred, A, w, b, lookahead=True)
+    a2, t2, _ = _run(bandred, A, w, b, lookahead=False)
     assert np.array_equal(np.tril(a1), np.tril(a2))
     assert np.array_equal(t1, t2)
 
@@ -164,7 +168,8 @@ def test_known_spectrum_config(bandred, orc):
     assert err["band_trunc"] <= 1e-14 * n
 
 
-@pytest.mark.parametrize("n,w,b", [(700, 96, 64), (1000, 128, 128), (300, 16, 16)])
+@pytest.mark.parametrize("n,w,b", [(700, 96, 64), (1000, 128, 128), (300, 16, 16),
+                                   (900, 128, 48)])
 def test_sy2sb_graph_replay_matches_eager(bandred, n, w, b):
     print(f"case sy2sb graph n={n} w={w} b={b}", flush=True)
     """The whole reduction captured in a HIP graph (after one eager call of
