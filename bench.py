@@ -380,6 +380,8 @@ def main():
                     help="warm up and run the steps only (for rocprofv3)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="one serial warm-up and the serial per-kernel step only (for rocprofv3)")
+    ap.add_argument("--launch", choices=["graph", "eager"], default="graph",
+                    help="time replays of a captured HIP graph (default) or eager calls")
     ap.add_argument("--serial-only", action="store_true",
                     help="a plain device copy of the matrix (calibrates rocprofv3's FETCH_SIZE "
                          "and WRITE_SIZE counters) and one serial reduction (for rocprofv3 --pmc)")
@@ -466,8 +468,8 @@ def main():
         with torch.cuda.graph(graph, stream=cs):
             run_eager()
     torch.cuda.synchronize()
-    run64 = graph.replay
-    log(f"bench: timing {args.steps} steps (graph replay)")
+    run64 = graph.replay if args.launch == "graph" else run_eager
+    log(f"bench: timing {args.steps} steps ({args.launch})")
     t_wall = time.perf_counter()
     times = time_steps(run64, restore, args.steps, stream)
     t_wall = time.perf_counter() - t_wall
@@ -552,7 +554,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "w": w, "b": b,
                    **({"m": p["m"]} if is_ge else {}), "prec": "fp64", "lookahead": True,
-                   "launch": "HIP graph replay of the whole reduction",
+                   "launch": ("HIP graph replay of the whole reduction" if args.launch == "graph"
+                              else "eager calls (two streams)"),
                    "input": p["kind"] + (f", {p.get('spectrum')} spectrum" if "spectrum" in p else "")
                    + f", seed {p['seed']}"},
         "pct_fp64_peak": 100.0 * gflops / 1e3 / PEAK_TFLOPS["fp64"],

@@ -111,6 +111,7 @@ struct DevState {
   hipEvent_t done = nullptr;  // completion of the previous call's work
   hipStream_t aux = nullptr;  // look-ahead (panel) stream
   hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_c = nullptr, ev_d = nullptr;
+  hipEvent_t ev_h = nullptr;  // head of a look-ahead panel (see panel_factor)
   int *flags = nullptr;       // [0] status, [1] abort   (device)
   // batched calls: uploaded matrix tables, a pinned staging copy, the work
   // counter and the per-workgroup scratch
@@ -170,6 +171,7 @@ static int dev_state(DevState **out) {
     BR_HIP_CHECK(hipEventCreateWithFlags(&st.ev_b, hipEventDisableTiming));
     BR_HIP_CHECK(hipEventCreateWithFlags(&st.ev_c, hipEventDisableTiming));
     BR_HIP_CHECK(hipEventCreateWithFlags(&st.ev_d, hipEventDisableTiming));
+    BR_HIP_CHECK(hipEventCreateWithFlags(&st.ev_h, hipEventDisableTiming));
     BR_HIP_CHECK(hipStreamCreateWithFlags(&st.aux, hipStreamNonBlocking));
     BR_HIP_CHECK(hipMalloc((void **)&st.flags, 64));
     BR_HIP_CHECK(hipMemset(st.flags, 0, 64));
@@ -480,8 +482,19 @@ static int panel_columns(Ctx &cx, bool rowmajor, double *P, int64_t ldp, int m, 
 static int panel_factor(Ctx &cx, bool rowmajor, double *P, int64_t ldp, int m, int nb, double *V,
                         int64_t ldv, double *tau, double *T, int ldt, PanelWs &pw,
                         unsigned *counter, int *flag, int *structure, int method, int panel_rows,
-                        hipStream_t s) {
+                        hipStream_t s, hipEvent_t head_ev = nullptr, int head_at = 0,
+                        bool *head_done = nullptr) {
+  // head_ev (optional) is recorded on s at point head_at of the CholeskyQR2
+  // path: 1 after the first Gram product, 2 after the first Cholesky and
+  // inverse, 3 after the second Gram product, 4 after the second Cholesky
   int rc;
+  auto head = [&](int at) -> int {
+    if (head_ev && head_at == at) {
+      BR_HIP_CHECK(hipEventRecord(head_ev, s));
+      if (head_done) *head_done = true;
+    }
+    return 0;
+  };
   // a square panel's last column has no rows below the diagonal (tau = 0 by
   // the Householder convention): factor it column by column
   if (m <= nb) method = 1;
@@ -501,11 +514,15 @@ static int panel_factor(Ctx &cx, bool rowmajor, double *P, int64_t ldp, int m, i
   rc = gemm(cx, C_PANEL, rowmajor ? A_N : A_T, rowmajor ? B_T : B_N, P_F64, nb, nb, m, P, ldp, P,
             ldp, pw.G, nb, 1.0, 0.0, s);
   if (rc) return rc;
+  rc = head(1);
+  if (rc) return rc;
   {
     ProfScope p2(C_PANEL_SMALL, 0.0, s);
     rc = launch_chol_inv(pw.G, nb, nb, 1e-10, pw.R1, pw.R1i, flag, structure, s);
     if (rc) return rc;
   }
+  rc = head(2);
+  if (rc) return rc;
   // Q1 = P R1^-1 ; G2 = Q1^T Q1 ; R2 = chol(G2), R2^-1
   rc = gemm(cx, C_PANEL, rowmajor ? A_T : A_N, B_N, P_F64, m, nb, nb, P, ldp, pw.R1i, nb, pw.Q1,
             m, 1.0, 0.0, s, flag, 0);
@@ -513,11 +530,15 @@ static int panel_factor(Ctx &cx, bool rowmajor, double *P, int64_t ldp, int m, i
   rc = gemm(cx, C_PANEL, A_T, B_N, P_F64, nb, nb, m, pw.Q1, m, pw.Q1, m, pw.G2, nb, 1.0, 0.0, s,
             flag, 0);
   if (rc) return rc;
+  rc = head(3);
+  if (rc) return rc;
   {
     ProfScope p2(C_PANEL_SMALL, 0.0, s);
     rc = launch_chol_inv(pw.G2, nb, nb, 1e-6, pw.R2, pw.R2i, flag, nullptr, s);
     if (rc) return rc;
   }
+  rc = head(4);
+  if (rc) return rc;
   // Qtop = Q1(0:nb, :) R2^-1 ; LU with signs, T, U^-1
   rc = gemm(cx, C_PANEL, A_N, B_N, P_F64, nb, nb, nb, pw.Q1, m, pw.R2i, nb, pw.Qtop, nb, 1.0, 0.0,
             s, flag, 0);
@@ -637,12 +658,25 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
   rc = launch_fill(tau, n - w, 0.0, s); if (rc) return rc;
 
   // panel `it` (columns c .. c+pb-1) and its Wt = V T, on stream q
+  // Variant V1: the trailing update waits for the head of the look-ahead
+  // panel, its sparsity check and first Gram product P^T P (point 1 of
+  // panel_factor), so that this wide product runs on the whole chip before the
+  // SYMM takes it; the rest of the panel (latency-bound b x b kernels and
+  // narrower products) then runs beside the update.  Without it a graph replay,
+  // which dispatches both branches at once, stretched both (SY2SB n=16384,
+  // w=256, b=128: 164.2 ms against 151.2 with the wait; eager calls, where the
+  // host issues the panel's launches before the SYMM's, 150.7 against 152.8).
+  const int head_at = (lookahead && 2 * b <= w) ? 1 : 0;
+  bool head_recorded = false;  // set by the last factor() call that recorded ev_h
   auto factor = [&](int it, Ctx &cx, hipStream_t q) -> int {
     const int c = it * b, pb = std::min(b, nref - c), r = c + w, j = n - r;
     double *V = WVbuf[it & 1] + (int64_t)pb * j;
+    const bool h = head_at > 0 && q != s;
+    head_recorded = false;
     int e = panel_factor(cx, false, A + r + (int64_t)c * lda, lda, j, pb, V, j, tau + c,
                          Tb[it & 1], pb, pw, counters + it, pflags + 2 * it,
-                         pstruct + (size_t)it * 2 * kNbMax, method, panel_rows, q);
+                         pstruct + (size_t)it * 2 * kNbMax, method, panel_rows, q,
+                         h ? st->ev_h : nullptr, head_at, &head_recorded);
     if (e) return e;
     return gemm(cx, C_GEMM_SMALL, A_N, B_N, P_F64, j, pb, pb, V, j, Tb[it & 1], pb, Wtb[it & 1], j,
                 1.0, 0.0, q);
@@ -695,6 +729,7 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
     if (v1) {
       rc = fork_next();
       if (rc) return rc;
+      if (head_recorded) BR_HIP_CHECK(hipStreamWaitEvent(s, st->ev_h, 0));
     }
     rc = update_a1(a1L, a1w);  // A1^R (empty in Variant V2)
     if (rc) return rc;
