@@ -67,15 +67,18 @@ def pmc_traffic(cls, workload):
     return val if cur.startswith(sha) else None
 
 
-def serial_call(br, A, is_ge, w, b):
+def reduce_fn(br, kind):
+    """The binding call of a workload kind: sy (SY2SB), ge (GE2GB to upper
+    triangular-band form) or lu (GE2GB to the equal-bandwidth form)."""
+    return {"sy": br.sy2sb, "ge": br.ge2gb, "lu": br.ge2gb_lu}[kind]
+
+
+def serial_call(br, A, kind, w, b):
     """One FP64 reduction without look-ahead: every kernel alone on the GPU."""
-    if is_ge:
-        br.ge2gb(A, w, b, prec="fp64", lookahead=False)
-    else:
-        br.sy2sb(A, w, b, prec="fp64", lookahead=False)
+    reduce_fn(br, kind)(A, w, b, prec="fp64", lookahead=False)
 
 
-def serial_roofline(br, A, restore, is_ge, w, b, workload):
+def serial_roofline(br, A, restore, kind, w, b, workload):
     """Per-launch HIP events (on the stream each kernel runs on) over one
     serial reduction.  The roofline entry is the contraction class with the
     most device time; the panel classes (latency-bound single-workgroup and
@@ -85,7 +88,7 @@ def serial_roofline(br, A, restore, is_ge, w, b, workload):
     restore()
     torch.cuda.synchronize()
     br.bandred_profile_enable(True)
-    serial_call(br, A, is_ge, w, b)
+    serial_call(br, A, kind, w, b)
     torch.cuda.synchronize()
     prof_serial = br.bandred_profile_read()
     br.bandred_profile_enable(False)
@@ -129,12 +132,23 @@ def cpu_baseline(p, A_dev):
 
     orc = oracle.get()
     is_ge = "m" in p
+    is_lu = p.get("form") == "lu"
     n, w = p["n"], p["w"]
     m = p["m"] if is_ge else n
     A = A_dev.cpu().numpy()
-    run = (lambda k: orc.ge2gb(A, w, ncols=k)) if is_ge else (lambda k: orc.sy2sb(A, w, ncols=k))
+    if is_lu:
+        run = lambda k: orc.ge2gb_lu(A, w, ncols=k)  # noqa: E731
+    elif is_ge:
+        run = lambda k: orc.ge2gb(A, w, ncols=k)  # noqa: E731
+    else:
+        run = lambda k: orc.sy2sb(A, w, ncols=k)  # noqa: E731
 
     def flops_of(k):
+        if is_lu:
+            # step c: left reflector on an (m-c-w) x (n-c) block, right one on
+            # an (m-c-1) x (n-c-w) block, 4 flops per entry each
+            return sum(4.0 * max(m - c - w, 0) * (n - c) + 4.0 * (m - c - 1) * max(n - c - w, 0)
+                       for c in range(k))
         if is_ge:
             # step c: left reflector on an (m-c) x (n-c) block, right one on an
             # (m-c-1) x (n-c-w) block, 4 flops per entry each
@@ -411,6 +425,8 @@ def main():
     assert A.stride(0) == 1
     n, w, b = p["n"], p["w"], p["b"]
     is_ge = "m" in p
+    kind = "lu" if p.get("form") == "lu" else ("ge" if is_ge else "sy")
+    lower = w if kind == "lu" else 0
     flops = nominal_flops(p)
 
     def restore():
@@ -419,12 +435,10 @@ def main():
     out = {}
 
     def runner(prec):
-        if is_ge:
-            def run():
-                out["tau"] = br.ge2gb(A, w, b, prec=prec)
-        else:
-            def run():
-                out["tau"] = br.sy2sb(A, w, b, prec=prec)
+        fn = reduce_fn(br, kind)
+
+        def run():
+            out["tau"] = fn(A, w, b, prec=prec)
         return run
 
     run_eager = runner("fp64")
@@ -437,7 +451,7 @@ def main():
         del B
         restore()
         torch.cuda.synchronize()
-        serial_call(br, A, is_ge, w, b)
+        serial_call(br, A, kind, w, b)
         torch.cuda.synchronize()
         print(json.dumps({"metric": METRIC, "workload": args.workload, "serial_only": True,
                           "copy_bytes": 2 * A0.numel() * 8}))
@@ -446,9 +460,9 @@ def main():
         # the serial per-kernel step alone, after one serial warm-up: under
         # rocprofv3 every launch of the trace is one the roofline figure covers
         restore()
-        serial_call(br, A, is_ge, w, b)
+        serial_call(br, A, kind, w, b)
         torch.cuda.synchronize()
-        roofline, _ = serial_roofline(br, A, restore, is_ge, w, b, args.workload)
+        roofline, _ = serial_roofline(br, A, restore, kind, w, b, args.workload)
         print(json.dumps({"metric": METRIC, "workload": args.workload, "roofline": roofline}))
         return
     log(f"bench: warmup {args.warmup}")
@@ -486,7 +500,7 @@ def main():
         log("bench: accuracy of the FP64 result")
         if is_ge:
             tq, tp = out["tau"]
-            acc = metrics.ge2gb_errors(A0, A, tq, tp, w, svd=False)
+            acc = metrics.ge2gb_errors(A0, A, tq, tp, w, svd=False, lower=lower)
         else:
             acc = metrics.sy2sb_errors(A0, torch.tril(A), out["tau"], w, eig=False)
         acc = {k: v for k, v in acc.items() if v is not None}
@@ -500,7 +514,7 @@ def main():
     torch.cuda.synchronize()
     prof = br.bandred_profile_read()
     br.bandred_profile_enable(False)
-    roofline, prof_serial = serial_roofline(br, A, restore, is_ge, w, b, args.workload)
+    roofline, prof_serial = serial_roofline(br, A, restore, kind, w, b, args.workload)
     breakdown = {k: {"ms": round(v["ms"], 3), "launches": v["launches"],
                      "tflops": (v["flops"] / (v["ms"] / 1e3) / 1e12) if v["ms"] > 0 and v["flops"] > 0 else None}
                  for k, v in prof.items() if v["launches"]}
@@ -528,7 +542,7 @@ def main():
             if not args.no_accuracy:
                 if is_ge:
                     tq, tp = out["tau"]
-                    e = metrics.ge2gb_errors(A0, A, tq, tp, w, svd=False)
+                    e = metrics.ge2gb_errors(A0, A, tq, tp, w, svd=False, lower=lower)
                 else:
                     e = metrics.sy2sb_errors(A0, torch.tril(A), out["tau"], w, eig=False)
                 f["backward"] = e["backward"]
@@ -553,7 +567,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "w": w, "b": b,
-                   **({"m": p["m"]} if is_ge else {}), "prec": "fp64", "lookahead": True,
+                   **({"m": p["m"]} if is_ge else {}),
+                   **({"band": "lower and upper bandwidth w"} if kind == "lu" else {}),
+                   "prec": "fp64", "lookahead": True,
                    "launch": ("HIP graph replay of the whole reduction" if args.launch == "graph"
                               else "eager calls (two streams)"),
                    "input": p["kind"] + (f", {p.get('spectrum')} spectrum" if "spectrum" in p else "")

@@ -658,15 +658,16 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
   rc = launch_fill(tau, n - w, 0.0, s); if (rc) return rc;
 
   // panel `it` (columns c .. c+pb-1) and its Wt = V T, on stream q
-  // Variant V1: the trailing update waits for the head of the look-ahead
-  // panel, its sparsity check and first Gram product P^T P (point 1 of
-  // panel_factor), so that this wide product runs on the whole chip before the
-  // SYMM takes it; the rest of the panel (latency-bound b x b kernels and
-  // narrower products) then runs beside the update.  Without it a graph replay,
-  // which dispatches both branches at once, stretched both (SY2SB n=16384,
-  // w=256, b=128: 164.2 ms against 151.2 with the wait; eager calls, where the
-  // host issues the panel's launches before the SYMM's, 150.7 against 152.8).
-  const int head_at = (lookahead && 2 * b <= w) ? 1 : 0;
+  // The trailing update that runs beside a look-ahead panel waits for the
+  // panel's head, its sparsity check and first Gram product P^T P (point 1 of
+  // panel_factor), so that this wide product runs on the whole chip; the rest
+  // of the panel (latency-bound b x b kernels and narrower products) then runs
+  // beside the update.  Without it a graph replay, which dispatches both
+  // branches at once, stretched both.  Measured: Variant V1 (SY2SB n=16384,
+  // w=256, b=128) 164.2 -> 151.2 ms (eager calls, where the host issues the
+  // panel's launches before the SYMM's, 150.7 against 152.8); Variant V2
+  // (n=16384, w=b=128, the rest of the SYR2K waiting) 160.4 -> 158.6 ms.
+  const int head_at = lookahead ? 1 : 0;
   bool head_recorded = false;  // set by the last factor() call that recorded ev_h
   auto factor = [&](int it, Ctx &cx, hipStream_t q) -> int {
     const int c = it * b, pb = std::min(b, nref - c), r = c + w, j = n - r;
@@ -746,6 +747,7 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
     if (a2L > 0) {
       rc = fork_next();
       if (rc) return rc;
+      if (head_recorded) BR_HIP_CHECK(hipStreamWaitEvent(s, st->ev_h, 0));
     }
     // the rest beside the next panel: in chunks (see update_chunks)
     if (has_next && ps != s)
@@ -826,11 +828,15 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
   rc = launch_fill(taup, n, 0.0, s); if (rc) return rc;
 
   // left panel `it` (columns c .. c+pb-1) and Wtq = Vq Tq, on stream q
+  // a panel forked beside an update records the head event (see sy2sb_impl)
+  bool head_recorded = false;
   auto left_panel = [&](int it, Ctx &c_, hipStream_t q) -> int {
     const int c = it * b, pb = std::min(b, n - c), i = m - c;
+    head_recorded = false;
     int r = panel_factor(c_, false, A + c + (int64_t)c * lda, lda, i, pb, Vq, i, tauq + c, Tq, pb,
                          pw, counters + 2 * it, pflags + 4 * it,
-                         pstruct + (size_t)(2 * it) * 2 * kNbMax, method, panel_rows, q);
+                         pstruct + (size_t)(2 * it) * 2 * kNbMax, method, panel_rows, q,
+                         q != s ? st->ev_h : nullptr, 1, &head_recorded);
     if (r) return r;
     return gemm(c_, C_GEMM_SMALL, A_N, B_N, P_F64, i, pb, pb, Vq, i, Tq, pb, Wtq, i, 1.0, 0.0, q);
   };
@@ -839,9 +845,11 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
     const int c = it * b, pb = std::min(b, n - c);
     const int pr = std::max(0, std::min(pb, n - w - 1 - c));
     const int c0 = c + w, jr = n - c0;
+    head_recorded = false;
     int r = panel_factor(c_, true, A + c + (int64_t)c0 * lda, lda, jr, pr, Up, jr, taup + c, Tp, pr,
                          pw, counters + 2 * it + 1, pflags + 4 * it + 2,
-                         pstruct + (size_t)(2 * it + 1) * 2 * kNbMax, method, panel_rows, q);
+                         pstruct + (size_t)(2 * it + 1) * 2 * kNbMax, method, panel_rows, q,
+                         q != s ? st->ev_h : nullptr, 1, &head_recorded);
     if (r) return r;
     return gemm(c_, C_GEMM_SMALL, A_N, B_N, P_F64, jr, pr, pr, Up, jr, Tp, pr, Wtp, jr, 1.0, 0.0, q);
   };
@@ -880,6 +888,7 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
         BR_HIP_CHECK(hipStreamWaitEvent(ps, st->ev_c, 0));
         rc = right_panel(it, cxp, ps);  // (3) overlaps the rest of (2)
         if (rc) return rc;
+        if (head_recorded) BR_HIP_CHECK(hipStreamWaitEvent(s, st->ev_h, 0));
         BR_HIP_CHECK(hipEventRecord(st->ev_d, ps));
         rc = gemm_chunked(cx, C_GEMM_UPD, A_N, B_N, prec, i - top, ne, pb, Vq + top, i, Zb, pb,
                           E + top, lda, -1.0, 1.0, s);
@@ -912,6 +921,7 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
           BR_HIP_CHECK(hipStreamWaitEvent(ps, st->ev_a, 0));
           rc = left_panel(it + 1, cxp, ps);  // next (1) overlaps the rest of (4)
           if (rc) return rc;
+          if (head_recorded) BR_HIP_CHECK(hipStreamWaitEvent(s, st->ev_h, 0));
           BR_HIP_CHECK(hipEventRecord(st->ev_b, ps));
           if (jr > lcols) {
             rc = gemm_chunked(cx, C_GEMM_UPD, A_N, B_T, prec, md, jr - lcols, pr, Xb, md,
@@ -1033,6 +1043,7 @@ static int ge2gb_lu_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, dou
   rc = launch_fill(tauq, n, 0.0, s); if (rc) return rc;
   rc = launch_fill(taup, n, 0.0, s); if (rc) return rc;
 
+  bool head_recorded = false;  // the left panel forked last recorded ev_h (see sy2sb_impl)
   auto widths = [&](int c, int *pbl, int *pbr) {
     *pbl = std::max(0, std::min(b, nl - c));
     *pbr = std::max(0, std::min(b, nr - c));
@@ -1047,7 +1058,8 @@ static int ge2gb_lu_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, dou
       double *Vl = XV[k] + (int64_t)pbr * jl;  // [X | Vl]: Vl after the pbr columns of X
       int r = panel_factor(c_, false, A + (c + w) + (int64_t)c * lda, lda, jl, pbl, Vl, jl,
                            tauq + c, Tl[k], pbl, pw, counters + 2 * it, pflags + 4 * it,
-                           pstruct + (size_t)(2 * it) * 2 * kNbMax, method, panel_rows, q);
+                           pstruct + (size_t)(2 * it) * 2 * kNbMax, method, panel_rows, q,
+                           q != s ? st->ev_h : nullptr, 1, &head_recorded);
       if (r) return r;
       r = gemm(c_, C_GEMM_SMALL, A_N, B_N, P_F64, jl, pbl, pbl, Vl, jl, Tl[k], pbl, Wtl[k], jl,
                1.0, 0.0, q);
@@ -1070,7 +1082,11 @@ static int ge2gb_lu_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, dou
       BR_HIP_CHECK(hipEventRecord(st->ev_a, s));
       BR_HIP_CHECK(hipStreamWaitEvent(ps, st->ev_a, 0));
     }
-    return panels(it, cxp, ps);
+    head_recorded = false;
+    int r = panels(it, cxp, ps);
+    if (r) return r;
+    if (head_recorded) BR_HIP_CHECK(hipStreamWaitEvent(s, st->ev_h, 0));
+    return 0;
   };
   auto join = [&]() -> int {
     if (ps != s) {

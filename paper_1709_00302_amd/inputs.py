@@ -34,6 +34,10 @@ WORKLOADS = {
     "sy2sb_n16384_w128": dict(kind="sym_known", n=16384, w=128, b=128, spectrum="graded", seed=3),
     "ge2gb_24576x12288_w128": dict(kind="ge_known", m=24576, n=12288, w=128, b=128, seed=4),
     "batched_2048_w16": dict(kind="batch", count=2048, w=16, b=16, seed=5),
+    # the equal-bandwidth form (Sec. 3.3) of the rectangular workload: lower and
+    # upper bandwidth 64, a band as wide as the triangular one of w = 128
+    "ge2gb_lu_24576x12288_w64": dict(kind="ge_known", form="lu", m=24576, n=12288, w=64, b=64,
+                                     seed=4),
     # look-ahead Variant V1 (2b <= w: the next panel lies in A1, Sec. 2.2)
     "sy2sb_n16384_w256": dict(kind="sym_normal", n=16384, w=256, b=128, seed=6),
 }
