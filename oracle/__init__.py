@@ -63,6 +63,8 @@ class Oracle:
         lib.oracle_apply_refl.argtypes = [ctypes.c_int, _c_i64, _c_i64, _c_i64, _c_dp, _c_i64,
                                           _c_dp, ctypes.c_int, _c_i64, _c_dp, _c_i64]
         lib.oracle_apply_refl.restype = ctypes.c_int
+        lib.oracle_tridiag_eigvals.argtypes = [_c_i64, _c_dp, _c_dp, _c_dp]
+        lib.oracle_tridiag_eigvals.restype = ctypes.c_int
         lib.oracle_house.argtypes = [_c_i64, _c_dp, _c_i64, _c_dp]
         lib.oracle_house.restype = ctypes.c_double
         lib.oracle_threads.argtypes = []
@@ -165,6 +167,35 @@ class Oracle:
         if info != 0:
             raise ValueError(f"oracle_apply_refl returned {info}")
         return C
+
+    def tridiag_eigvals(self, d, e):
+        """Eigenvalues (ascending) of the symmetric tridiagonal matrix with
+        diagonal d and off-diagonal e, by bisection on Sturm counts."""
+        d = np.ascontiguousarray(d, dtype=np.float64)
+        n = d.size
+        e = np.ascontiguousarray(e, dtype=np.float64)
+        ebuf = np.zeros(max(n, 1), dtype=np.float64)
+        ebuf[: max(n - 1, 0)] = e[: max(n - 1, 0)]
+        lam = np.zeros(max(n, 1), dtype=np.float64)
+        info = self.lib.oracle_tridiag_eigvals(n, self._ptr(d), self._ptr(ebuf), self._ptr(lam))
+        if info != 0:
+            raise ValueError(f"oracle_tridiag_eigvals returned {info}")
+        return lam[:n]
+
+    def band_eigvals(self, Aout, w: int):
+        """Eigenvalues of the symmetric band matrix held in the band (0 <= i-j
+        <= w) of a reduced matrix: its Householder tridiagonalisation (the
+        oracle's reduction at w = 1, an orthogonal similarity), then
+        bisection.  Any tridiagonalisation Z^T B Z with Z e_0 = e_0 has the
+        same eigenvalues; its entries are not unique to rounding."""
+        Aout = np.asarray(Aout, dtype=np.float64)
+        n = Aout.shape[0]
+        i = np.arange(n)
+        dd = i[:, None] - i[None, :]
+        B = np.where((dd >= 0) & (dd <= w), Aout, 0.0)
+        B = B + np.tril(B, -1).T
+        T, _ = self.sy2sb(B, 1)
+        return self.tridiag_eigvals(np.diag(T).copy(), np.diag(T, -1).copy())
 
     def sy2sb_q(self, Aout, tau, w: int, C, trans: bool = False):
         """Q C or Q^T C for the result of ``sy2sb``."""

@@ -462,3 +462,67 @@ int oracle_apply_refl(int rowstore, int64_t off, int64_t nrefl, int64_t len,
   free(v);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Eigenvalues of a symmetric tridiagonal matrix (the last step of the       */
+/* two-stage eigenvalue pipeline that follows the band reduction)            */
+/* ------------------------------------------------------------------------ */
+
+/* Number of eigenvalues of T = tridiag(e, d, e) smaller than x: the number of
+ * negative pivots of the LDL^T factorisation of T - x I (Sylvester's law of
+ * inertia; the Sturm sequence count of Golub and Van Loan, Sec. 8.4).  A
+ * pivot that is exactly zero is replaced by -pivmin, as if x had been moved by
+ * a tiny amount. */
+static int64_t sturm_count(int64_t n, const double *d, const double *e, double x,
+                           double pivmin) {
+  int64_t cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  if (q < 0.0) ++cnt;
+  for (int64_t i = 1; i < n; ++i) {
+#if ORACLE_MUTANT == 10
+    q = (d[i] - x) + e[i - 1] * e[i - 1] / q; /* planted: wrong sign of the update */
+#else
+    q = (d[i] - x) - e[i - 1] * e[i - 1] / q;
+#endif
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+/* All eigenvalues of the n x n symmetric tridiagonal matrix with diagonal d
+ * and off-diagonal e (n-1 entries), ascending, by bisection: eigenvalue k is
+ * the point where the count of eigenvalues below x passes from <= k to > k.
+ * The search starts from the Gershgorin interval and halves it until the two
+ * ends are adjacent doubles (or equal). */
+int oracle_tridiag_eigvals(int64_t n, const double *d, const double *e, double *lam) {
+  if (n < 0) return -1;
+  if (n > 0 && (d == NULL || lam == NULL)) return -2;
+  if (n > 1 && e == NULL) return -3;
+  if (n == 0) return 0;
+  double lo = d[0], hi = d[0], emax2 = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0);
+    if (d[i] - r < lo) lo = d[i] - r;
+    if (d[i] + r > hi) hi = d[i] + r;
+    if (i < n - 1 && e[i] * e[i] > emax2) emax2 = e[i] * e[i];
+  }
+  const double pivmin = 2.2250738585072014e-308 * (emax2 > 1.0 ? emax2 : 1.0);
+  const double pad = 2.220446049250313e-16 * (fabs(lo) > fabs(hi) ? fabs(lo) : fabs(hi)) * 4.0 +
+                     pivmin;
+  lo -= pad;
+  hi += pad;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t k = 0; k < n; ++k) {
+    double a = lo, b = hi;
+    for (int it = 0; it < 2200; ++it) {
+      const double mid = 0.5 * (a + b);
+      if (mid <= a || mid >= b) break; /* a and b adjacent */
+      if (sturm_count(n, d, e, mid, pivmin) > k) b = mid;
+      else a = mid;
+    }
+    lam[k] = 0.5 * (a + b);
+  }
+  return 0;
+}

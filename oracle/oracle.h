@@ -67,6 +67,14 @@ int oracle_apply_refl(int rowstore, int64_t off, int64_t nrefl, int64_t len,
                       const double *A, int64_t lda, const double *tau, int trans,
                       int64_t k, double *C, int64_t ldc);
 
+/* All eigenvalues (ascending) of the n x n symmetric tridiagonal matrix with
+ * diagonal d (n entries) and off-diagonal e (n-1 entries), by bisection on
+ * the Sturm count (number of negative pivots of LDL^T of T - x I), each
+ * interval halved until its ends are adjacent doubles.  The eigenvalue step
+ * after the band and tridiagonal reductions (the paper's pipeline ends with
+ * LAPACK's DSTERF, Sec. 4.3). */
+int oracle_tridiag_eigvals(int64_t n, const double *d, const double *e, double *lam);
+
 /* Householder vector of x (length L, stride inc): on return x[0] is left
  * alone, x[1:] holds v[1:], *beta the new leading entry; returns tau. */
 double oracle_house(int64_t L, double *x, int64_t inc, double *beta);
