@@ -343,6 +343,31 @@ def bench_batched(args, br, inputs, metrics):
         forms["per_matrix_launches"] = {"gflops": flops / (m3 / 1e3) / 1e9, "ms_per_step": m3,
                                         "batched_speedup": m3 / ms}
 
+    pipeline = None
+    if kind == "sy" and not args.no_pipeline:
+        # the two-stage eigenvalue pipeline the paper times after its first
+        # stage (Sec. 4.3): band -> tridiagonal, then the eigenvalues, on the
+        # band of the last timed result
+        log("bench: stage 2 and eigenvalues")
+        t2, t3 = [], []
+        for _ in range(2):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e2 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            dg, eg = br.sb2st(A, w, check=False)
+            e1.record(stream)
+            lam = br.tridiag_eigvals(dg, eg)
+            e2.record(stream)
+            torch.cuda.synchronize()
+            t2.append(e0.elapsed_time(e1))
+            t3.append(e1.elapsed_time(e2))
+        pipeline = {"stage1_ms": ms, "sb2st_ms": min(t2), "tridiag_eig_ms": min(t3),
+                    "total_ms": ms + min(t2) + min(t3)}
+        if "lam" in p:
+            ref = torch.sort(torch.as_tensor(p["lam"], dtype=torch.float64)).values
+            pipeline["eig_err_vs_known"] = float((lam.cpu() - ref).abs().max() / ref.abs().max())
+
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle, bounded sample)")
@@ -376,6 +401,7 @@ def bench_batched(args, br, inputs, metrics):
         "accuracy": acc,
         "roofline": roofline,
         "forms": forms,
+        "pipeline": pipeline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res))
@@ -390,6 +416,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="skip timing stage 2 and the eigenvalues after SY2SB")
     ap.add_argument("--profile-only", action="store_true",
                     help="warm up and run the steps only (for rocprofv3)")
     ap.add_argument("--roofline-only", action="store_true",

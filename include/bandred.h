@@ -174,6 +174,30 @@ BANDRED_API int bandred_ge2gb_apply(int side, int form, int trans, int64_t m, in
                         const double *tau, int64_t k, double *C, int64_t ldc,
                         void *stream);
 
+/* Stage 2 of a two-stage symmetric eigensolver (the paper's pipeline after
+ * its first stage, Sec. 4.3): the symmetric band B (bandwidth w) held in the
+ * band 0 <= i-j <= w of A (as bandred_sy2sb leaves it) is reduced to a
+ * symmetric tridiagonal T = Z^T B Z (Z orthogonal, Z e_0 = e_0) by
+ * Householder bulge chasing; on return d (n entries) holds the diagonal of
+ * T and e (n-1 entries) its subdiagonal.  T has the eigenvalues of B; its
+ * entries are determined by B only up to signs and rounding (two stable
+ * tridiagonalisations of one band agree in the spectrum, not entry by
+ * entry).  A is only read; Z is not kept.
+ *   n (arg 1) >= 0, w (arg 2) >= 1, A (arg 3, device), lda (arg 4 >= n),
+ *   d, e (args 5, 6, device), stream (arg 7).
+ * Asynchronous; runtime failures (a bounded wait between the sweeps that
+ * gave up) are reported by bandred_status. */
+BANDRED_API int bandred_sb2st(int64_t n, int64_t w, const double *A, int64_t lda, double *d,
+                  double *e, void *stream);
+
+/* All eigenvalues of the symmetric tridiagonal matrix with diagonal d (n
+ * entries) and subdiagonal e (n-1 entries), ascending, into lam (n
+ * entries); all device pointers.  Bisection on Sturm counts, accurate to a
+ * few units of 2 eps times the Gershgorin bound of |T|.  Args: n (1), d (2),
+ * e (3), lam (4), stream (5).  Asynchronous. */
+BANDRED_API int bandred_tridiag_eigvals(int64_t n, const double *d, const double *e, double *lam,
+                            void *stream);
+
 /* For callers that cannot allocate device memory: code under HIP stream
  * capture with no earlier eager call, serving loops that must not allocate,
  * harnesses that forbid hipMalloc.  Same reduction and arguments as

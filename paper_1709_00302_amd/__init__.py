@@ -73,6 +73,8 @@ def load(path: str = LIB_PATH):
     lib.bandred_tune.argtypes = [ctypes.c_int, _i64, _i64, _i64, ctypes.c_int, ctypes.c_int,
                                  ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
                                  ctypes.c_int]
+    lib.bandred_sb2st.argtypes = [_i64, _i64, _vp, _i64, _vp, _vp, _vp]
+    lib.bandred_tridiag_eigvals.argtypes = [_i64, _vp, _vp, _vp, _vp]
     lib.bandred_sy2sb_noalloc.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, ctypes.c_int, _vp]
     lib.bandred_sy2sb_batched.argtypes = [_i64, ctypes.POINTER(_i64), _i64, _i64,
                                           ctypes.POINTER(_vp), ctypes.POINTER(_i64),
@@ -91,7 +93,7 @@ def load(path: str = LIB_PATH):
                  "bandred_profile_read",
                  "bandred_status", "bandred_set_wait_limit_us", "bandred_release",
                  "bandred_ge2gb_lu", "bandred_sy2sb_apply_q", "bandred_ge2gb_apply",
-                 "bandred_tune"):
+                 "bandred_tune", "bandred_sb2st", "bandred_tridiag_eigvals"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -151,6 +153,14 @@ def bandred_tune(kind, m, n, w, prec=FP64, force=False):
     _check("bandred_tune", rc)
     ms = {int(buf[2 * i]): buf[2 * i + 1] for i in range(16) if buf[2 * i] > 0}
     return int(b.value), ms
+
+
+def bandred_sb2st(n, w, A, lda, d, e, stream=None) -> int:
+    return load().bandred_sb2st(n, w, A, lda, d, e, stream)
+
+
+def bandred_tridiag_eigvals(n, d, e, lam, stream=None) -> int:
+    return load().bandred_tridiag_eigvals(n, d, e, lam, stream)
 
 
 def bandred_sy2sb_noalloc(n, w, b, A, lda, tau, prec=FP64, stream=None) -> int:
@@ -325,6 +335,33 @@ def ge2gb_apply(Aout, tau, w: int, C, side: str = "u", equal_band: bool = False,
                              _stream_handle(stream))
     _check("bandred_ge2gb_apply", rc)
     return C
+
+
+def sb2st(Aout, w: int, stream=None, check: bool = True):
+    """Band (0 <= i-j <= w of the column-major CUDA tensor Aout) to symmetric
+    tridiagonal form; returns (d, e) device tensors."""
+    import torch
+
+    n = Aout.shape[0]
+    lda = _colmajor_ld(Aout, n)
+    d = torch.zeros(max(n, 1), dtype=torch.float64, device=Aout.device)
+    e = torch.zeros(max(n - 1, 1), dtype=torch.float64, device=Aout.device)
+    h = _stream_handle(stream)
+    _check("bandred_sb2st", bandred_sb2st(n, w, Aout.data_ptr(), lda, d.data_ptr(), e.data_ptr(), h))
+    _check_status("bandred_sb2st", h, check)
+    return d[:n], e[: max(n - 1, 0)]
+
+
+def tridiag_eigvals(d, e, stream=None):
+    """Eigenvalues (ascending) of the symmetric tridiagonal matrix (d, e)."""
+    import torch
+
+    n = d.shape[0]
+    lam = torch.zeros(max(n, 1), dtype=torch.float64, device=d.device)
+    ep = e.data_ptr() if e.numel() else None
+    _check("bandred_tridiag_eigvals",
+           bandred_tridiag_eigvals(n, d.data_ptr(), ep, lam.data_ptr(), _stream_handle(stream)))
+    return lam[:n]
 
 
 def sy2sb_batched(mats, w: int, b: int | None = None, prec="fp64", stream=None,

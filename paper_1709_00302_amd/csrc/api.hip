@@ -1264,6 +1264,68 @@ static int apply_impl(int rowstore, int64_t off, int64_t nrefl, int64_t len, con
 }
 
 // ---------------------------------------------------------------------------
+// Stage 2 of the eigenvalue pipeline: the band left by SY2SB to tridiagonal
+// form (bulge chasing, stage2.hip), and the tridiagonal matrix's eigenvalues.
+// ---------------------------------------------------------------------------
+static int sb2st_impl(int64_t n64, int64_t w64, const double *A, int64_t lda, double *dg,
+                      double *e, hipStream_t s) {
+  if (n64 == 0) return 0;
+  if (n64 > ((int64_t)1 << 30)) return BANDRED_ERR_UNSUPPORTED;
+  const int n = (int)n64;
+  const int w = (int)std::min<int64_t>(w64, std::max<int64_t>(n64 - 1, 1));
+  DevState *st = nullptr;
+  int rc = dev_state(&st);
+  if (rc) return rc;
+  const int64_t ldab = 2 * (int64_t)w + 1;
+  const size_t need = round_up((size_t)ldab * n * 8, 256) + round_up((size_t)n * 4, 256) + 1024;
+  std::lock_guard<std::mutex> lk(g_mu);
+  bool capturing = false;
+  rc = capture_check(s, need, *st, &capturing);
+  if (rc) return rc;
+  rc = ws_reserve(*st, need);
+  if (rc) return rc;
+  Arena ar(st->base);
+  double *AB = ar.take<double>((size_t)ldab * n);
+  int *progress = ar.take<int>(n);
+  unsigned *ctr = ar.take<unsigned>(64);
+  if (!capturing) BR_HIP_CHECK(hipStreamWaitEvent(s, st->done, 0));
+  rc = launch_fill_u32((unsigned *)progress, n, 0u, s); if (rc) return rc;
+  rc = launch_fill_u32(ctr, 1, 0u, s); if (rc) return rc;
+  rc = launch_fill_u32((unsigned *)st->flags, 2, 0u, s); if (rc) return rc;
+  g_last_flags[current_dev_index()] = st->flags;
+  rc = launch_sb2st(A, lda, n, w, AB, ldab, ctr, progress, st->flags, st->timeout_ticks,
+                    st->num_cu, dg, e, s);
+  if (rc) return rc;
+  if (!capturing) BR_HIP_CHECK(hipEventRecord(st->done, s));
+  return 0;
+}
+
+static int tridiag_eig_impl(int64_t n64, const double *dg, const double *e, double *lam,
+                            hipStream_t s) {
+  if (n64 == 0) return 0;
+  if (n64 > ((int64_t)1 << 30)) return BANDRED_ERR_UNSUPPORTED;
+  DevState *st = nullptr;
+  int rc = dev_state(&st);
+  if (rc) return rc;
+  const size_t need = 1024;
+  std::lock_guard<std::mutex> lk(g_mu);
+  bool capturing = false;
+  rc = capture_check(s, need, *st, &capturing);
+  if (rc) return rc;
+  rc = ws_reserve(*st, need);
+  if (rc) return rc;
+  Arena ar(st->base);
+  double *bounds = ar.take<double>(8);
+  if (!capturing) BR_HIP_CHECK(hipStreamWaitEvent(s, st->done, 0));
+  rc = launch_fill_u32((unsigned *)st->flags, 2, 0u, s); if (rc) return rc;
+  g_last_flags[current_dev_index()] = st->flags;
+  rc = launch_tridiag_eig(dg, e, (int)n64, bounds, lam, s);
+  if (rc) return rc;
+  if (!capturing) BR_HIP_CHECK(hipEventRecord(st->done, s));
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
 // Batched SY2SB: one persistent launch over a table of matrices sorted by
 // decreasing order; matrices the kernel cannot hold (b > 16 or n - w > 1024)
 // go through the single-matrix path on the same stream afterwards.
@@ -1591,6 +1653,26 @@ int bandred_ge2gb_apply(int side, int form, int trans, int64_t m, int64_t n, int
   if (ldc < (len > 1 ? len : 1)) return -13;
   return apply_impl(side, off, nrefl, len, A, lda, tau, trans, k, C, ldc, (int)b,
                     (hipStream_t)stream);
+}
+
+int bandred_sb2st(int64_t n, int64_t w, const double *A, int64_t lda, double *d, double *e,
+                  void *stream) {
+  if (n < 0) return -1;
+  if (w < 1) return -2;
+  if (n > 0 && A == nullptr) return -3;
+  if (lda < (n > 1 ? n : 1)) return -4;
+  if (n > 0 && d == nullptr) return -5;
+  if (n > 1 && e == nullptr) return -6;
+  return sb2st_impl(n, w, A, lda, d, e, (hipStream_t)stream);
+}
+
+int bandred_tridiag_eigvals(int64_t n, const double *d, const double *e, double *lam,
+                            void *stream) {
+  if (n < 0) return -1;
+  if (n > 0 && d == nullptr) return -2;
+  if (n > 1 && e == nullptr) return -3;
+  if (n > 0 && lam == nullptr) return -4;
+  return tridiag_eig_impl(n, d, e, lam, (hipStream_t)stream);
 }
 
 int bandred_sy2sb_noalloc(int64_t n, int64_t w, int64_t b, double *A, int64_t lda, double *tau,

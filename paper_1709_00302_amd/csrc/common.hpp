@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "../../include/bandred.h"
 
 namespace br {
@@ -121,6 +123,12 @@ int launch_extract_v(const double *A, int64_t lda, int rowstore, int64_t r0, int
 // (kind 0: sy2sb, 1: ge2gb, 2: ge2gb_lu)
 int tune_pick(int kind, int64_t m, int64_t n, int64_t w, int prec, hipStream_t s, int *b_out);
 int tune_lookup(int kind, int64_t m, int64_t n, int64_t w, int prec);
+// stage 2 (stage2.hip): band -> tridiagonal by bulge chasing, tridiagonal eigenvalues
+int launch_sb2st(const double *A, int64_t lda, int n, int w, double *AB, int64_t ldab,
+                 unsigned *sweep_ctr, int *progress, int *flags, long long timeout_ticks, int nwg,
+                 double *dg, double *e, hipStream_t s);
+int launch_tridiag_eig(const double *dg, const double *e, int n, double *bounds, double *lam,
+                       hipStream_t s);
 constexpr int kPackedMax = kNbMax * (kNbMax + 1) / 2;
 int launch_fill(double *p, int64_t count, double v, hipStream_t s);
 int launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t s);

@@ -1,0 +1,428 @@
+// stage2.hip -- the steps after the band reduction in a two-stage symmetric
+// eigenvalue solver (gfx950): band -> tridiagonal by Householder bulge
+// chasing, and the eigenvalues of the tridiagonal matrix by multisection on
+// Sturm counts.  The paper times this pipeline with SBR's band-to-tridiagonal
+// routine and LAPACK's DSTERF after its first stage (Sec. 4.3).
+//
+// Band to tridiagonal.  The symmetric band B (bandwidth w) is copied into a
+// band store with room for the bulges: AB(k, c) = B(c + k, c), 0 <= k <= 2w.
+// Sweep s makes column s tridiagonal: step 0 builds the reflector that
+// annihilates B(s+2 : s+w, s) (rows S0 = s+1 .. s+w) and applies it to the
+// diagonal block S0 x S0 from both sides and to the block R1 x S0 below it
+// (R1 = s+w+1 .. s+2w) from the right, which fills R1 x S0 (the bulge).  Step
+// k >= 1 annihilates the first column of that bulge below its first row
+// (rows R_k = s+1+kw .. s+(k+1)w, column s+1+(k-1)w) with a reflector on R_k,
+// applies it from the left to the rest of the bulge block, from both sides to
+// R_k x R_k and from the right to the next block R_{k+1} x R_k, pushing the
+// bulge w rows down.  The rest of each bulge block is annihilated by the
+// following sweeps (their blocks are shifted by one row and column), so the
+// matrix never has more than 2w subdiagonals.
+//
+// Sweeps run concurrently: one persistent workgroup per sweep at a time,
+// sweeps claimed in increasing order from an atomic counter.  Step k >= 1 of
+// sweep s touches the elements (r, c) with r in s+1+kw .. s+(k+2)w and c in
+// s+1+(k-1)w .. s+(k+1)w (step 0: rows s+1 .. s+2w, columns s .. s+w); step
+// k' of sweep s+1 meets these only for k in k'-1 .. k'+2, so it may start once
+// sweep s-1 has finished k'+3 steps, after which no later step of sweep s
+// touches the same elements: every element sees the operations of the
+// sequential order, in that order.  The waits are bounded (wall
+// clock), and a workgroup that gives up raises an abort flag that releases
+// every other one.
+#include "common.hpp"
+
+namespace br {
+
+constexpr int kS2T = 512;      // threads of the bulge-chasing workgroup (8 waves)
+constexpr int kS2Lag = 3;      // steps sweep s-1 must be ahead of sweep s
+constexpr int kS2LD = kNbMax + 1;  // row stride of the LDS block (odd: no bank conflicts)
+
+struct Sb2stDesc {
+  double *AB;
+  int64_t ldab;
+  int n, w, nsweeps;
+  unsigned *sweep_ctr;
+  int *progress;               // steps finished per sweep
+  int *status, *abort_flag;
+  long long timeout_ticks;
+};
+
+__device__ __forceinline__ int sweep_steps(int n, int w, int s) {
+  // steps k = 0 .. K-1 with s + 1 + k w < n for k >= 1
+  const int rem = n - 1 - s;  // > 0
+  return 1 + (rem > w ? (rem - 1) / w : 0);
+}
+
+struct S2Lds {
+  double blk[kNbMax * kS2LD];  // one block of the step, row-major blk[r * kS2LD + c]
+  double v[kNbMax];
+  double p[kNbMax];
+  double red[kS2T / 64];
+  int go;
+  int sweep;
+};
+
+__device__ __forceinline__ double block_sum(double x, double *red) {
+  // all threads of the workgroup; result in every thread
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[wv] = x;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < kS2T / 64; ++i) t += red[i];
+  return t;
+}
+
+// The elements (t, j), t < rows, j < cols, of a block in column-major order,
+// kS2T apart: thread tid's q-th element is tid + q kS2T.  The (t, j) pairs
+// are stepped without integer division.
+struct Walk {
+  int t, j, dt, dj, rows;
+  __device__ Walk(int rows_) : rows(rows_) {
+    t = threadIdx.x % rows_;
+    j = threadIdx.x / rows_;
+    dt = kS2T % rows_;
+    dj = kS2T / rows_;
+  }
+  __device__ __forceinline__ void next() {
+    t += dt;
+    j += dj;
+    if (t >= rows) {
+      t -= rows;
+      ++j;
+    }
+  }
+};
+
+// Load a rows x cols block into LDS (src(t, j), dst(t, j, value)) with every
+// global load of the thread issued before its first LDS store.
+constexpr int kS2Per = (kNbMax * kNbMax + kS2T - 1) / kS2T;
+template <class Src, class Dst>
+__device__ __forceinline__ void stage_in(int rows, int cols, Src src, Dst dst) {
+  double r[kS2Per];
+  Walk a(rows);
+#pragma unroll
+  for (int q = 0; q < kS2Per; ++q) {
+    r[q] = (a.j < cols) ? src(a.t, a.j) : 0.0;
+    a.next();
+  }
+  Walk b(rows);
+#pragma unroll
+  for (int q = 0; q < kS2Per; ++q) {
+    if (b.j < cols) dst(b.t, b.j, r[q]);
+    b.next();
+  }
+}
+
+template <class F>
+__device__ __forceinline__ void for_block(int rows, int cols, F f) {
+  Walk a(rows);
+  for (int q = 0; q < kS2Per && a.j < cols; ++q) {
+    f(a.t, a.j);
+    a.next();
+  }
+}
+
+// Band-store accesses of the bulge chasing: relaxed atomics at agent scope.
+// The sweeps hand their blocks to one another across workgroups (possibly on
+// different XCDs, whose L2 caches are not coherent with each other); with
+// these accesses the data does not sit dirty in one XCD's L2, so the release
+// and acquire fences of the progress hand-off stay cheap.
+__device__ __forceinline__ double bld(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void bst(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// one step (s, k) of the bulge chasing.  Every block the step touches is
+// brought into LDS with coalesced loads (a column of a block is a contiguous
+// piece of a band-store column), updated there and written back.
+__device__ void sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s, int k) {
+  const int n = d.n, w = d.w, tid = threadIdx.x;
+  const int64_t ld = d.ldab;
+  double *AB = d.AB;
+  auto ptr = [&](int r, int c) { return AB + ((int64_t)(r - c) + (int64_t)c * ld); };
+  auto get = [&](int r, int c) { return bld(ptr(r, c)); };
+  auto put = [&](int r, int c, double v) { bst(ptr(r, c), v); };
+  int cx, rx, L;
+  if (k == 0) {
+    cx = s;
+    rx = s + 1;
+    L = min(w, n - 1 - s);
+  } else {
+    cx = s + 1 + (k - 1) * w;
+    rx = s + 1 + k * w;
+    L = min(w, n - rx);
+  }
+  if (L < 2) return;
+  // (1) the reflector that annihilates column cx below row rx
+  double x = 0.0;
+  if (tid < L) {
+    x = get(rx + tid, cx);
+    sh.v[tid] = x;
+  }
+  const double sig2 = block_sum(tid >= 1 && tid < L ? x * x : 0.0, sh.red);
+  const double alpha = sh.v[0];
+  if (sig2 == 0.0) return;  // H = I
+  const double nrm = sqrt(alpha * alpha + sig2);
+  const double beta = (alpha < 0.0) ? nrm : -nrm;
+  const double tau = (beta - alpha) / beta;
+  const double dv = alpha - beta;
+  __syncthreads();
+  if (tid < L) {
+    sh.v[tid] = (tid == 0) ? 1.0 : x / dv;
+    put(rx + tid, cx, (tid == 0) ? beta : 0.0);
+  }
+  __syncthreads();
+  double *blk = sh.blk;
+  // (2) the rest of the bulge block, rows rx .. rx+L-1, columns cx+1 ..
+  //     cx+w-1, from the left: blk[t][j] = B(rx + t, cx + 1 + j)
+  if (k >= 1) {
+    const int nc = w - 1;
+    stage_in(L, nc, [&](int t, int j) { return get(rx + t, cx + 1 + j); },
+             [&](int t, int j, double a) { blk[t * kS2LD + j] = a; });
+    __syncthreads();
+    if (tid < nc) {  // z_j = v^T blk(:, j)
+      double z = 0.0;
+      for (int t = 0; t < L; ++t) z += sh.v[t] * blk[t * kS2LD + tid];
+      sh.p[tid] = tau * z;
+    }
+    __syncthreads();
+    for_block(L, nc, [&](int t, int j) {
+      put(rx + t, cx + 1 + j, blk[t * kS2LD + j] - sh.p[j] * sh.v[t]);
+    });
+    __syncthreads();
+  }
+  // (3) the diagonal block R x R from both sides: p = tau D v,
+  //     q = p - (tau p^T v / 2) v, D -= v q^T + q v^T (lower part stored;
+  //     the block is mirrored in LDS)
+  stage_in(L, L, [&](int t, int u) { return t >= u ? get(rx + t, rx + u) : 0.0; },
+           [&](int t, int u, double a) {
+             if (t >= u) {
+               blk[t * kS2LD + u] = a;
+               blk[u * kS2LD + t] = a;
+             }
+           });
+  __syncthreads();
+  double pt = 0.0;
+  if (tid < L) {
+    for (int u = 0; u < L; ++u) pt += blk[tid * kS2LD + u] * sh.v[u];
+    pt *= tau;
+  }
+  const double pv = block_sum(tid < L ? pt * sh.v[tid] : 0.0, sh.red);
+  const double Kc = 0.5 * tau * pv;
+  if (tid < L) sh.p[tid] = pt - Kc * sh.v[tid];  // q
+  __syncthreads();
+  for_block(L, L, [&](int t, int u) {
+    if (t >= u) put(rx + t, rx + u, blk[t * kS2LD + u] - (sh.v[t] * sh.p[u] + sh.p[t] * sh.v[u]));
+  });
+  __syncthreads();
+  // (4) the block below, rows rx+w .. rx+2w-1, from the right:
+  //     blk[i][u] = B(r2 + i, rx + u)
+  const int r2 = rx + w;
+  const int m2 = min(rx + 2 * w, n) - r2;
+  if (m2 > 0) {
+    stage_in(m2, L, [&](int i, int u) { return get(r2 + i, rx + u); },
+             [&](int i, int u, double a) { blk[i * kS2LD + u] = a; });
+    __syncthreads();
+    if (tid < m2) {
+      double y = 0.0;
+      for (int u = 0; u < L; ++u) y += blk[tid * kS2LD + u] * sh.v[u];
+      sh.p[tid] = tau * y;
+    }
+    __syncthreads();
+    for_block(m2, L, [&](int i, int u) {
+      put(r2 + i, rx + u, blk[i * kS2LD + u] - sh.p[i] * sh.v[u]);
+    });
+  }
+}
+
+__device__ __forceinline__ long long s2_ticks() { return (long long)wall_clock64(); }
+
+__global__ __launch_bounds__(kS2T) void k_sb2st(Sb2stDesc d) {
+  __shared__ S2Lds sh;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) sh.sweep = (int)atomicAdd(d.sweep_ctr, 1u);
+    __syncthreads();
+    const int s = sh.sweep;
+    __syncthreads();
+    if (s >= d.nsweeps) return;
+    const int K = sweep_steps(d.n, d.w, s);
+    const int Kp = (s > 0) ? sweep_steps(d.n, d.w, s - 1) : 0;
+    for (int k = 0; k < K; ++k) {
+      if (s > 0) {
+        if (tid == 0) {
+          const int need = min(k + kS2Lag, Kp);
+          int ok = 1;
+          const long long t0 = s2_ticks();
+          // relaxed polling; one acquire fence once the word is reached
+          while (__hip_atomic_load(d.progress + (s - 1), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT) < need) {
+            if (__hip_atomic_load(d.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+              ok = 0;
+              break;
+            }
+            if (s2_ticks() - t0 > d.timeout_ticks) {
+              __hip_atomic_store(d.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              __hip_atomic_store(d.status, (int)BANDRED_ERR_TIMEOUT, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+              ok = 0;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+          }
+          // acquire (agent scope) once, by this thread; the workgroup barrier
+          // below orders the other threads after it
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          sh.go = ok;
+        }
+        __syncthreads();
+        if (!sh.go) return;
+      }
+      sb2st_step(d, sh, s, k);
+      // publish: every thread's stores, then the progress word
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __syncthreads();
+      if (tid == 0)
+        __hip_atomic_store(d.progress + s, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// AB(k, c) = A(c + k, c) for k <= w, zero for w < k <= 2w
+__global__ void k_band_copy(const double *A, int64_t lda, int n, int w, double *AB, int64_t ldab) {
+  const int64_t total = (int64_t)ldab * n;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(idx % ldab);
+    const int64_t c = idx / ldab;
+    double v = 0.0;
+    if (k <= w && c + k < n) v = A[(c + k) + c * lda];
+    AB[idx] = v;
+  }
+}
+
+__global__ void k_tridiag_extract(const double *AB, int64_t ldab, int n, double *dg, double *e) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    dg[i] = AB[(int64_t)i * ldab];
+    if (i < n - 1) e[i] = AB[1 + (int64_t)i * ldab];
+  }
+}
+
+int launch_sb2st(const double *A, int64_t lda, int n, int w, double *AB, int64_t ldab,
+                 unsigned *sweep_ctr, int *progress, int *flags, long long timeout_ticks, int nwg,
+                 double *dg, double *e, hipStream_t s) {
+  {
+    const int64_t total = ldab * (int64_t)n;
+    int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_band_copy, dim3(blocks), dim3(256), 0, s, A, lda, n, w, AB, ldab);
+    BR_HIP_CHECK(hipGetLastError());
+  }
+  const int nsweeps = std::max(0, n - 2);
+  if (w > 1 && nsweeps > 0) {
+    Sb2stDesc dd{};
+    dd.AB = AB; dd.ldab = ldab; dd.n = n; dd.w = w; dd.nsweeps = nsweeps;
+    dd.sweep_ctr = sweep_ctr; dd.progress = progress;
+    dd.status = flags; dd.abort_flag = flags + 1; dd.timeout_ticks = timeout_ticks;
+    hipLaunchKernelGGL(k_sb2st, dim3(std::max(1, std::min(nwg, nsweeps))), dim3(kS2T), 0, s, dd);
+    BR_HIP_CHECK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_tridiag_extract, dim3(std::max(1, std::min(1024, (n + 255) / 256))),
+                     dim3(256), 0, s, (const double *)AB, ldab, n, dg, e);
+  BR_HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Eigenvalues of the tridiagonal matrix: multisection on Sturm counts.  One
+// wave per eigenvalue index k: the 64 lanes count the eigenvalues below 64
+// points spread evenly inside the current interval [a, b] (which holds
+// eigenvalue k), and the interval shrinks to the subinterval where the count
+// passes k, 65 times narrower per round, until a and b are adjacent doubles
+// or within 2 eps of the matrix's Gershgorin scale.  The count is the number
+// of negative pivots of LDL^T of T - x I (a zero pivot counts as -pivmin).
+// ---------------------------------------------------------------------------
+__global__ void k_tridiag_bounds(const double *dg, const double *e, int n, double *bounds) {
+  __shared__ double slo[256], shi[256], se2[256];
+  const int t = threadIdx.x;
+  double lo = 1e308, hi = -1e308, e2 = 0.0;
+  for (int i = t; i < n; i += 256) {
+    const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0);
+    lo = fmin(lo, dg[i] - r);
+    hi = fmax(hi, dg[i] + r);
+    if (i < n - 1) e2 = fmax(e2, e[i] * e[i]);
+  }
+  slo[t] = lo; shi[t] = hi; se2[t] = e2;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off) {
+      slo[t] = fmin(slo[t], slo[t + off]);
+      shi[t] = fmax(shi[t], shi[t + off]);
+      se2[t] = fmax(se2[t], se2[t + off]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double pivmin = 2.2250738585072014e-308 * fmax(se2[0], 1.0);
+    const double scale = fmax(fabs(slo[0]), fabs(shi[0]));
+    const double pad = 4.0 * 2.220446049250313e-16 * scale + pivmin;
+    bounds[0] = slo[0] - pad;
+    bounds[1] = shi[0] + pad;
+    bounds[2] = pivmin;
+    bounds[3] = scale;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tridiag_eig(const double *dg, const double *e, int n,
+                                                     const double *bounds, double *lam) {
+  const int lane = threadIdx.x & 63;
+  const int k = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+  if (k >= n) return;
+  double a = bounds[0], b = bounds[1];
+  const double pivmin = bounds[2];
+  const double tol = 2.0 * 2.220446049250313e-16 * bounds[3];
+  for (int round = 0; round < 64; ++round) {
+    if (b - a <= tol) break;
+    const double x = a + (b - a) * (double)(lane + 1) * (1.0 / 65.0);
+    // Sturm count below x
+    int cnt = 0;
+    double q = dg[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += (q < 0.0);
+    for (int i = 1; i < n; ++i) {
+      const double ei = e[i - 1];
+      q = (dg[i] - x) - (ei * ei) / q;
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += (q < 0.0);
+    }
+    // first point whose count exceeds k: eigenvalue k lies below it
+    const unsigned long long above = __ballot(cnt > k);
+    const int f = above ? __builtin_ctzll(above) : 64;
+    const double xf = __shfl(x, f < 64 ? f : 63);
+    const double xp = __shfl(x, f > 0 ? f - 1 : 0);
+    const double na = (f > 0) ? xp : a;
+    const double nb = (f < 64) ? xf : b;
+    if (na == a && nb == b) break;  // no progress: a and b (nearly) adjacent
+    a = na;
+    b = nb;
+  }
+  if (lane == 0) lam[k] = 0.5 * (a + b);
+}
+
+int launch_tridiag_eig(const double *dg, const double *e, int n, double *bounds, double *lam,
+                       hipStream_t s) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(k_tridiag_bounds, dim3(1), dim3(256), 0, s, dg, e, n, bounds);
+  BR_HIP_CHECK(hipGetLastError());
+  const int64_t threads = (int64_t)n * 64;
+  hipLaunchKernelGGL(k_tridiag_eig, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, dg,
+                     e, n, (const double *)bounds, lam);
+  BR_HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
+}  // namespace br
