@@ -424,6 +424,9 @@ def main():
                     help="one serial warm-up and the serial per-kernel step only (for rocprofv3)")
     ap.add_argument("--launch", choices=["graph", "eager"], default="graph",
                     help="time replays of a captured HIP graph (default) or eager calls")
+    ap.add_argument("--stage2-only", action="store_true",
+                    help="one SY2SB, then band -> tridiagonal and the eigenvalues twice "
+                         "(for rocprofv3)")
     ap.add_argument("--serial-only", action="store_true",
                     help="a plain device copy of the matrix (calibrates rocprofv3's FETCH_SIZE "
                          "and WRITE_SIZE counters) and one serial reduction (for rocprofv3 --pmc)")
@@ -446,7 +449,20 @@ def main():
     stream = torch.cuda.current_stream()
 
     log(f"bench: building workload {args.workload} on the GPU")
-    p = inputs.make_on_device(args.workload, device="cuda")
+    if args.serial_only and inputs.WORKLOADS[args.workload]["kind"] == "sym_known":
+        # the counters do not depend on the values: a symmetric N(0,1) matrix of
+        # the same shape, without the QR of the known-spectrum construction
+        # (which has crashed inside the solver library under the counter
+        # profiler)
+        p = dict(inputs.WORKLOADS[args.workload])
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(int(p["seed"]))
+        Z = torch.randn(p["n"], p["n"], generator=gen, device="cuda", dtype=torch.float64)
+        U = torch.triu(Z)
+        p["A"] = (U + torch.triu(U, 1).T).T.contiguous().T
+        del Z, U
+    else:
+        p = inputs.make_on_device(args.workload, device="cuda")
     A0 = p["A"]
     A = torch.empty_like(A0)  # same column-major strides
     A.copy_(A0)
@@ -492,6 +508,22 @@ def main():
         torch.cuda.synchronize()
         roofline, _ = serial_roofline(br, A, restore, kind, w, b, args.workload)
         print(json.dumps({"metric": METRIC, "workload": args.workload, "roofline": roofline}))
+        return
+    if args.stage2_only:
+        restore()
+        run_eager()
+        torch.cuda.synchronize()
+        res = {"metric": METRIC, "workload": args.workload, "stage2_only": True}
+        for rep in range(2):
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record(stream)
+            dg, eg = br.sb2st(A, w, check=False)
+            e1.record(stream)
+            lam = br.tridiag_eigvals(dg, eg)
+            e2.record(stream)
+            torch.cuda.synchronize()
+            res[f"rep{rep}"] = {"sb2st_ms": e0.elapsed_time(e1), "tridiag_eig_ms": e1.elapsed_time(e2)}
+        print(json.dumps(res))
         return
     log(f"bench: warmup {args.warmup}")
     for _ in range(max(1, args.warmup)):
