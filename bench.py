@@ -9,8 +9,8 @@ The matrix is restored from a pristine device copy before every step, outside
 the timed events; inputs are resident in HBM when timing starts.
 
 value = nominal 4 n^3 / 3 flops / median step time (the paper's flop rule,
-Sec. 4), FP64.  Also reported: the FP32 and split-FP32 trailing-update forms on
-the same matrix, accuracy of the timed result, the dominant kernel against
+Sec. 4), FP64.  Also reported: the FP32, split-FP32 and int8 exact-split
+trailing-update forms on the same matrix, accuracy of the timed result, the dominant kernel against
 the FP64 matrix-core peak, and the CPU oracle timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SY2SB/GE2GB GFLOP/s, FP64 vs split-FP32 at n=16384; % MFMA peak; backward err"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split32": 157.3}
+# the exact-split form runs on int8 MFMA (5.0 POP/s dense)
 
 
 def log(msg):
@@ -589,7 +590,7 @@ def main():
     forms["fp64_eager"] = {"gflops": flops / (statistics.median(te) / 1e3) / 1e9,
                            "ms_per_step": statistics.median(te)}
     if not args.no_forms:
-        for prec in ("fp32", "split32"):
+        for prec in ("fp32", "split32", "int8split"):
             log(f"bench: form {prec}")
             run = runner(prec)
             restore()

@@ -53,8 +53,18 @@ typedef enum {
   BANDRED_FP64 = 0,           /* FP64 MFMA, FP64 accumulation */
   BANDRED_FP32_UPDATE = 1,    /* operands rounded to FP32, FP32 MFMA and accumulation,
                                  result added to the FP64 matrix */
-  BANDRED_SPLIT32_UPDATE = 2  /* x = hi + lo (both FP32); hi*hi + hi*lo + lo*hi on FP32
+  BANDRED_SPLIT32_UPDATE = 2, /* x = hi + lo (both FP32); hi*hi + hi*lo + lo*hi on FP32
                                  MFMA with FP32 accumulation, summed in FP64 */
+  BANDRED_INT8_SPLIT_UPDATE = 3 /* exact split (error-free slicing): each row of the left
+                                 operand and column of the right one scaled by a power of
+                                 two and cut into 8 int8 digits of 7 bits; the 36 digit
+                                 products of order <= 9 run on int8 MFMA with exact int32
+                                 sums and are combined in FP64.  Per term of the inner
+                                 dimension K the dropped part is below 2^-52 of the
+                                 product of the row and column scales, under the
+                                 worst-case error of an FP64 dot product.  Not in the paper (which is
+                                 FP64 throughout).  Work space grows by about
+                                 8 (n + 2w) n bytes (SY2SB; m and n for GE2GB) */
 } bandred_prec_t;
 
 /* Optional knobs for the _ex entry points (pass NULL for defaults). */
@@ -209,7 +219,9 @@ BANDRED_API int bandred_tridiag_eigvals(int64_t n, const double *d, const double
  * (n - w) * (120 b + b^2 / 8) bytes plus O(b^2 + b w): n <= 3455 at
  * w = b = 128, n <= 8092 at w = b = 64, n <= 16607 at w = b = 32; a larger
  * problem returns BANDRED_ERR_UNSUPPORTED before any work is enqueued (as
- * does a call while profiling is enabled).  Every call on a device shares
+ * does a call while profiling is enabled).  BANDRED_INT8_SPLIT_UPDATE needs
+ * about 8 (n - w) (n - w + 2 max(2b, w)) bytes more (its digit planes):
+ * n <= about 1970 at w = b = 128.  Every call on a device shares
  * that device's array and leaves its contents behind (each call clears what
  * it needs zeroed before use): calls that overlap on one device, on any
  * streams, race and give undefined results; the caller orders them.

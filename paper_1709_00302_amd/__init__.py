@@ -19,8 +19,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbandred.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "bandred.h")
 
-FP64, FP32_UPDATE, SPLIT32_UPDATE = 0, 1, 2
-PREC_NAMES = {"fp64": FP64, "fp32": FP32_UPDATE, "split32": SPLIT32_UPDATE}
+FP64, FP32_UPDATE, SPLIT32_UPDATE, INT8_SPLIT_UPDATE = 0, 1, 2, 3
+PREC_NAMES = {"fp64": FP64, "fp32": FP32_UPDATE, "split32": SPLIT32_UPDATE,
+              "int8split": INT8_SPLIT_UPDATE}
 
 
 class BandredUnavailable(RuntimeError):

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbandred.so")
 SOURCES = ["api.hip", "gemm.hip", "panel.hip", "recon.hip", "batched.hip", "backtrans.hip",
-           "tune.hip", "stage2.hip"]
+           "tune.hip", "stage2.hip", "ozaki.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

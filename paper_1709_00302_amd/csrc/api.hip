@@ -247,18 +247,90 @@ struct Ctx {
   hipStream_t s;
   double *part;
   size_t part_cap;  // doubles
+  char *oz = nullptr;  // digit planes of the exact-split products (P_OZ)
+  size_t oz_cap = 0;   // bytes
 };
+
+// ---------------------------------------------------------------------------
+// exact-split products (P_OZ, ozaki.hip)
+// ---------------------------------------------------------------------------
+// bytes of one product's slices: row maxima and exponents (two segments at
+// most) and the digit planes of op(A) (M rows) and op(B) (N columns) over K
+// (each segment padded to a multiple of 64)
+static size_t oz_need(int64_t M, int64_t N, int64_t K) {
+  const size_t Kp = round_up((size_t)K, 64) + 64;
+  return 6 * 256 + 24 * (size_t)(M + N) + (size_t)kOzS * (M + N) * Kp;
+}
+// bound over the products of a driver whose dimensions are at most L1, L2
+// (the matrix) and s2 (a block of reflectors), in any roles
+static size_t oz_bound(int64_t L1, int64_t L2, int64_t s2) {
+  const int64_t d[3] = {L1, L2, s2};
+  size_t m = 0;
+  for (int k = 0; k < 3; ++k)  // d[k] is the inner dimension
+    m = std::max(m, oz_need(d[(k + 1) % 3], d[(k + 2) % 3], d[k]));
+  return round_up(m, 256);
+}
+
+// C = alpha op(A) op(B) + beta C (E_AXPBY), or C -= op(A) op(B) on the lower
+// triangle of columns [c0, c1) (E_SYR2K), through int8 digit planes.  A rank-2k
+// update [P | Q] [R | S]^T passes ks = the width of P: the two halves of the
+// inner dimension get scales of their own.
+static int gemm_oz(Ctx &cx, int cls, int opa, int opb, int epi, int M, int N, int K, int ks,
+                   const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
+                   int64_t ldc, double alpha, double beta, int rot, int c0, int c1, double flops,
+                   hipStream_t s) {
+  if (!cx.oz || oz_need(M, N, K) > cx.oz_cap) return BANDRED_ERR_UNSUPPORTED;
+  int L0 = 0;
+  const int Kp = oz_plane_cols(K, ks, &L0);
+  Arena ar(cx.oz);
+  unsigned long long *mxa = ar.take<unsigned long long>(2 * (size_t)M);
+  unsigned long long *mxb = ar.take<unsigned long long>(2 * (size_t)N);
+  int *ea = ar.take<int>(2 * (size_t)M), *eb = ar.take<int>(2 * (size_t)N);
+  int8_t *PA = ar.take<int8_t>((size_t)kOzS * M * Kp);
+  int8_t *PB = ar.take<int8_t>((size_t)kOzS * N * Kp);
+  const int *abort = cx.st->flags + 1;
+  ProfScope ps(cls, flops, s);
+  int rc = oz_slice(A, lda, opa, M, K, ks, 0, 0, mxa, ea, PA, s);
+  if (rc) return rc;
+  rc = oz_slice(B, ldb, opb, N, K, ks, rot, 1, mxb, eb, PB, s);
+  if (rc) return rc;
+  if (epi == E_SYR2K)
+    return oz_gemm(E_SYR2K, PA, PB, ea, eb, M, N, Kp, L0, 1, Kp, C, ldc, 1.0, 0.0, nullptr, c0,
+                   c1, abort, s);
+  // one 64 x 64 workgroup per CU is resident: split k when the tiles do not
+  // fill the chip (chunks of at least 256, partial sums within the buffer)
+  const int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
+  int nk = 1;
+  if (tiles < cx.st->num_cu && Kp >= 512) {
+    nk = (int)std::min<int64_t>((2 * cx.st->num_cu + tiles - 1) / tiles, Kp / 256);
+    while (nk > 1 && (size_t)nk * M * N > cx.part_cap) --nk;
+  }
+  if (nk <= 1)
+    return oz_gemm(E_AXPBY, PA, PB, ea, eb, M, N, Kp, L0, 1, Kp, C, ldc, alpha, beta, nullptr, 0,
+                   0, abort, s);
+  const int kchunk = (int)round_up((size_t)(Kp + nk - 1) / nk, 64);
+  nk = (Kp + kchunk - 1) / kchunk;
+  rc = oz_gemm(E_PART, PA, PB, ea, eb, M, N, Kp, L0, nk, kchunk, nullptr, 0, 1.0, 0.0, cx.part,
+               0, 0, abort, s);
+  if (rc) return rc;
+  return launch_reduce_partials(cx.part, nk, M, N, alpha, C, ldc, beta, s, nullptr, 0, abort);
+}
 
 // C(M x N) = alpha op(A) op(B) + beta C, split over k when that fills the chip.
 static int gemm(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int K,
                 const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
                 int64_t ldc, double alpha, double beta, hipStream_t s,
                 const int *gate = nullptr, int gate_val = 0, double *C2 = nullptr,
-                int64_t ldc2 = 0, int c2_trans = 0, int lds_pad = 0) {
+                int64_t ldc2 = 0, int c2_trans = 0, int lds_pad = 0, int kseg = 0) {
   if (M <= 0 || N <= 0) return 0;
   if (K <= 0) {
     if (beta == 1.0) return 0;
     return BANDRED_ERR_UNSUPPORTED;  // never needed by the drivers
+  }
+  if (prec == P_OZ) {
+    if (gate || C2) return BANDRED_ERR_UNSUPPORTED;  // (only FP64 products use these)
+    return gemm_oz(cx, cls, opa, opb, E_AXPBY, M, N, K, kseg, A, lda, B, ldb, C, ldc, alpha, beta,
+                   0, 0, 0, 2.0 * M * N * (double)K, s);
   }
   GemmDesc d{};
   d.M = M; d.N = N; d.K = K;
@@ -329,6 +401,11 @@ static int gemm(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int 
 static int syr2k(Ctx &cx, int prec, int j, int pb, const double *WV, int64_t ldwv, double *A2,
                  int64_t lda, int c0, int c1, hipStream_t s, int lds_pad = 0) {
   if (c1 <= c0) return 0;
+  if (prec == P_OZ) {
+    const double r0 = (double)(j - c0), r1 = (double)(j - c1);
+    return gemm_oz(cx, C_SYR2K, A_N, B_TROT, E_SYR2K, j, j, 2 * pb, pb, WV, ldwv, WV, ldwv, A2,
+                   lda, 1.0, 0.0, pb, c0, c1, 2.0 * pb * (r0 * (r0 + 1) - r1 * (r1 + 1)), s);
+  }
   GemmDesc d{};
   d.lds_pad = lds_pad;
   d.abort = cx.st->flags + 1;
@@ -408,7 +485,7 @@ static int syr2k_chunked(Ctx &cx, int prec, int j, int pb, const double *WV, int
 // update_chunks() launches over column chunks of 128-multiples.
 static int gemm_chunked(Ctx &cx, int cls, int opa, int opb, int prec, int M, int N, int K,
                         const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
-                        int64_t ldc, double alpha, double beta, hipStream_t s) {
+                        int64_t ldc, double alpha, double beta, hipStream_t s, int kseg = 0) {
   const int64_t tiles = (int64_t)((M + 127) / 128) * ((N + 127) / 128);
   const int nck = (K <= 512) ? update_chunks(cx.st, tiles) : 1;
   const int nt = (N + 127) / 128;
@@ -418,7 +495,7 @@ static int gemm_chunked(Ctx &cx, int cls, int opa, int opb, int prec, int M, int
     const double *Bk = (opb == B_N) ? B + (int64_t)n0 * ldb : B + n0;
     int rc = gemm(cx, cls, opa, opb, prec, M, n1 - n0, K, A, lda, Bk, ldb,
                   C + (int64_t)n0 * ldc, ldc, alpha, beta, s, nullptr, 0, nullptr, 0, 0,
-                  M <= kUpdateCapBelow ? kUpdateCapLds : 0);
+                  M <= kUpdateCapBelow ? kUpdateCapLds : 0, kseg);
     if (rc) return rc;
     n0 = n1;
   }
@@ -615,6 +692,8 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
   need += PanelWs::bytes(jmax, b);
   need += 3 * round_up((size_t)(npan + 1) * 4, 256);     // counters, flags (2 per panel)
   need += round_up((size_t)(npan + 1) * 2 * kNbMax * 4, 256);  // panel structure
+  const size_t oz_sz = prec == P_OZ ? oz_bound(jmax, jmax, 2 * std::max(b, w)) : 0;
+  need += oz_sz;
   need += 8192;
   std::lock_guard<std::mutex> lk(g_mu);
   bool capturing = false;
@@ -645,6 +724,10 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
   int *pstruct = ar.take<int>((size_t)(npan + 1) * 2 * kNbMax);
 
   Ctx cxm{st, s, partm, part_main};
+  if (oz_sz) {
+    cxm.oz = ar.take<char>(oz_sz);
+    cxm.oz_cap = oz_sz;
+  }
   hipStream_t ps = lookahead ? st->aux : s;  // panel stream
   Ctx cxp{st, ps, partp, part_pan};
 
@@ -793,6 +876,8 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
   need += PanelWs::bytes(m, b);
   need += 3 * round_up((size_t)(2 * npan + 2) * 4, 256);
   need += round_up((size_t)(2 * npan + 2) * 2 * kNbMax * 4, 256);  // panel structure
+  const size_t oz_sz = prec == P_OZ ? oz_bound(m, n, 2 * std::max(b, w)) : 0;
+  need += oz_sz;
   need += 8192;
   std::lock_guard<std::mutex> lk(g_mu);
   bool capturing = false;
@@ -814,6 +899,10 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
   int *pflags = ar.take<int>(2 * (2 * npan + 2));
   int *pstruct = ar.take<int>((size_t)(2 * npan + 2) * 2 * kNbMax);
   Ctx cx{st, s, part, part_cap};
+  if (oz_sz) {
+    cx.oz = ar.take<char>(oz_sz);
+    cx.oz_cap = oz_sz;
+  }
   hipStream_t ps = la ? st->aux : s;  // panel stream
   Ctx cxp{st, ps, partp, part_pan};  // panels: their own split-k buffer on either stream
 
@@ -1006,6 +1095,8 @@ static int ge2gb_lu_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, dou
   need += PanelWs::bytes(std::max(jlmax, jrmax), b);
   need += 3 * round_up((size_t)(2 * npan + 2) * 4, 256);
   need += round_up((size_t)(2 * npan + 2) * 2 * kNbMax * 4, 256);
+  const size_t oz_sz = prec == P_OZ ? oz_bound(m, n, 2 * std::max(b, w)) : 0;
+  need += oz_sz;
   need += 8192;
   std::lock_guard<std::mutex> lk(g_mu);
   bool capturing = false;
@@ -1030,6 +1121,10 @@ static int ge2gb_lu_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, dou
   int *pflags = ar.take<int>(2 * (2 * npan + 2));
   int *pstruct = ar.take<int>((size_t)(2 * npan + 2) * 2 * kNbMax);
   Ctx cx{st, s, part, part_cap};
+  if (oz_sz) {
+    cx.oz = ar.take<char>(oz_sz);
+    cx.oz_cap = oz_sz;
+  }
   hipStream_t ps = la ? st->aux : s;
   Ctx cxp{st, ps, partp, part_pan};
 
@@ -1164,11 +1259,13 @@ static int ge2gb_lu_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, dou
       const int K = pbr + pbl;
       auto upd = [&](int r0, int r1, int c0, int c1, bool chunked) -> int {
         if (r1 <= r0 || c1 <= c0) return 0;
+        // (the exact-split form scales X and Vl apart: see gemm_oz)
         if (chunked)
           return gemm_chunked(cx, C_GEMM_UPD, A_N, B_T, prec, r1 - r0, c1 - c0, K, X + r0, jl,
-                              VZ[k] + c0, jr, D + r0 + (int64_t)c0 * lda, lda, -1.0, 1.0, s);
+                              VZ[k] + c0, jr, D + r0 + (int64_t)c0 * lda, lda, -1.0, 1.0, s, pbr);
         return gemm(cx, C_GEMM_UPD, A_N, B_T, prec, r1 - r0, c1 - c0, K, X + r0, jl, VZ[k] + c0,
-                    jr, D + r0 + (int64_t)c0 * lda, lda, -1.0, 1.0, s);
+                    jr, D + r0 + (int64_t)c0 * lda, lda, -1.0, 1.0, s, nullptr, 0, nullptr, 0, 0,
+                    0, pbr);
       };
       if (next && !v1 && ps != s) {
         rc = upd(0, jl, 0, aL, false);   // D11 and D21: the next left panel's columns
@@ -1527,7 +1624,8 @@ static int check_ge2gb(int64_t m, int64_t n, int64_t w, int64_t b, const double 
 }
 
 static int check_prec(int prec) {
-  return (prec == BANDRED_FP64 || prec == BANDRED_FP32_UPDATE || prec == BANDRED_SPLIT32_UPDATE)
+  return (prec == BANDRED_FP64 || prec == BANDRED_FP32_UPDATE || prec == BANDRED_SPLIT32_UPDATE ||
+          prec == BANDRED_INT8_SPLIT_UPDATE)
              ? 0
              : 1;
 }

@@ -17,7 +17,12 @@ constexpr int kNbMax = 128;     // widest panel (block size b) supported
 constexpr int kBK = 16;         // k-depth of one LDS stage of the GEMM kernels
 
 // Trailing-update arithmetic (matches bandred_prec_t).
-enum Prec { P_F64 = 0, P_F32 = 1, P_SPLIT = 2 };
+enum Prec { P_F64 = 0, P_F32 = 1, P_SPLIT = 2, P_OZ = 3 };
+
+// exact-split form (ozaki.hip): int8 digits per operand entry, and the k
+// range after which the int32 accumulators are folded into FP64
+constexpr int kOzS = 8;
+constexpr int kOzKF = 2048;
 
 // Operand access patterns of the GEMM kernels.
 //   A_N:   op(A)(i,k) = A[i + k*lda]
@@ -129,6 +134,19 @@ int launch_sb2st(const double *A, int64_t lda, int n, int w, double *AB, int64_t
                  double *dg, double *e, hipStream_t s);
 int launch_tridiag_eig(const double *dg, const double *e, int n, double *bounds, double *lam,
                        hipStream_t s);
+// exact-split products (ozaki.hip).  The inner dimension K is one segment,
+// or two ([0, ks) and [ks, K)) with scales of their own; the digit planes
+// hold each segment padded to a multiple of 64 (oz_plane_cols: total columns,
+// *L0 = where segment 1 starts).
+int oz_plane_cols(int K, int ks, int *L0);
+// op(A) (isB = 0) or op(B) (isB = 1) as rows of kOzS int8 digit planes
+// (rows x Kp each) with exponents ex[seg rows + r]; rmax is scratch of
+// 2 rows words of 64 bits
+int oz_slice(const double *X, int64_t ld, int op, int rows, int K, int ks, int rot, int isB,
+             unsigned long long *rmax, int *ex, int8_t *planes, hipStream_t s);
+int oz_gemm(int epi, const int8_t *PA, const int8_t *PB, const int *ea, const int *eb, int M,
+            int N, int Kp, int L0, int ksplit, int kchunk, double *C, int64_t ldc, double alpha,
+            double beta, double *part, int c0, int c1, const int *abort, hipStream_t s);
 constexpr int kPackedMax = kNbMax * (kNbMax + 1) / 2;
 int launch_fill(double *p, int64_t count, double v, hipStream_t s);
 int launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t s);

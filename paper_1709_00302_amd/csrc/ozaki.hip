@@ -1,0 +1,371 @@
+// ozaki.hip -- the exact-split form of the trailing-update products (gfx950).
+//
+// Not in the paper (which is FP64 only): a product C = op(A) op(B) whose
+// operands are split into int8 slices and multiplied on the int8 matrix
+// cores, where products accumulate exactly in int32 (the error-free slicing
+// of Ozaki, Ogita, Oishi and Rump, on integer units).
+//
+// The inner dimension is cut into one or two segments (the rank-2k updates
+// take [W | V] [V | W]^T as two: their halves differ in scale by the norm of
+// the matrix).  In segment s, row i of op(A) is scaled by 2^-e_si so that its
+// largest entry is below 1 in magnitude, and written as kOzS digits of 7 bits:
+//     a 2^-e_si = sum_{p=1..S} d_p 128^-p + r,   d_p in [-127, 127], |r| < 128^-S
+// (each digit the truncated integer part of the running remainder times 128,
+// all exact in FP64); column j of op(B) likewise with 2^-f_sj.  Then
+//     C_ij = sum_s 2^(e_si + f_sj) sum_t 128^-t sum_{p+q=t} sum_{k in s} d^A_p(i,k) d^B_q(k,j),
+// where the pairs with p + q > S + 1 are dropped.  Pairs of equal t share one
+// int32 accumulator, which the kernel folds into FP64 at the end of a segment
+// and every kOzKF terms of k (at most 8 x 2048 x 127^2 < 2^31 in magnitude,
+// so the int32 sums are exact).  With S = 8, per term of k the dropped pairs
+// (7 of order 10, each below 2^-56, and fewer of higher order) and the two
+// truncation remainders (each below 2^-56) add up to less than 2^-52 of
+// 2^(e_si + f_sj): the error of C_ij is below 2^-52 sum_s K_s 2^(e_si + f_sj),
+// under the worst-case bound of an FP64 dot product of length K.
+//
+// Slices are stored as planes: plane p of op(A) is M x Kp int8 with k
+// contiguous (each segment zero padded to a multiple of 64, Kp the sum),
+// plane q of op(B) N x Kp likewise, so that a lane's 16 bytes of an MFMA
+// operand are one 16-byte load.
+// v_mfma_i32_16x16x64_i8 (measured on gfx950): lane l supplies A(l % 16,
+// 16 (l / 16) + e) and B(16 (l / 16) + e, l % 16) as bytes e = 0..15 and
+// receives D(4 (l / 16) + e, l % 16) in element e.
+#include "common.hpp"
+
+namespace br {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// Operand x of a product as rows: row r, entry k is op(A)(r, k) (isB = 0) or
+// op(B)(k, r) (isB = 1).  The symmetric pattern reads the lower triangle
+// (entry (r, k) with r < k at (k, r)) and the rotated one shifts k by rot
+// modulo K.  Segment 0 is k < ks (all of K when ks = K), segment 1 the rest;
+// in the planes segment 0 takes columns [0, L0) and segment 1 [L0, Kp).
+struct OzSrc {
+  const double *X;
+  int64_t ld;
+  int op, isB, rows, K, rot;
+  int ks, L0, Kp;
+};
+__device__ __forceinline__ bool oz_row_contig(const OzSrc &s) {
+  return s.isB ? (s.op != B_N) : (s.op != A_T);  // A_N, A_SYM, B_T, B_TROT
+}
+__device__ __forceinline__ double oz_at(const OzSrc &s, int r, int k) {
+  if (!s.isB) {
+    if (s.op == A_N) return s.X[r + (int64_t)k * s.ld];
+    if (s.op == A_T) return s.X[k + (int64_t)r * s.ld];
+    return (r >= k) ? s.X[r + (int64_t)k * s.ld] : s.X[k + (int64_t)r * s.ld];
+  }
+  if (s.op == B_N) return s.X[k + (int64_t)r * s.ld];
+  if (s.op == B_T) return s.X[r + (int64_t)k * s.ld];
+  int kr = k + s.rot;
+  if (kr >= s.K) kr -= s.K;
+  return s.X[r + (int64_t)kr * s.ld];
+}
+
+// segment of plane block kb (64 columns) and the operand range it maps to
+__device__ __forceinline__ void oz_block(const OzSrc &s, int kb, int *seg, int *k0, int *klim) {
+  const int c = kb * 64;
+  if (c < s.L0) {
+    *seg = 0; *k0 = c; *klim = s.ks;
+  } else {
+    *seg = 1; *k0 = s.ks + (c - s.L0); *klim = s.K;
+  }
+}
+
+// Stage the 64 x 64 block (rows r0.., entries k0.. below klim) into t[r][k]
+// with loads that follow the contiguous dimension; other entries are 0.
+__device__ __forceinline__ void oz_stage(const OzSrc &s, int r0, int k0, int klim,
+                                         double (*t)[65]) {
+  const int tid = threadIdx.x;
+  const bool rc = oz_row_contig(s);
+#pragma unroll 4
+  for (int i = 0; i < 16; ++i) {
+    const int a = tid & 63, c = (tid >> 6) + 4 * i;
+    const int rl = rc ? a : c, kl = rc ? c : a;
+    const int r = r0 + rl, k = k0 + kl;
+    t[rl][kl] = (r < s.rows && k < klim) ? oz_at(s, r, k) : 0.0;
+  }
+}
+
+// largest |entry| of each row in each segment (rmax[seg rows + r]), as the
+// bits of a non-negative double (atomicMax on them orders like the values);
+// rmax is zero at launch.  A symmetric operand (one segment) visits the lower
+// blocks only and credits each entry to both its row and its column.
+__global__ __launch_bounds__(256) void k_oz_rowmax(OzSrc s, unsigned long long *rmax) {
+  const int kb = blockIdx.x, rb = blockIdx.y;
+  const bool sym = !s.isB && s.op == A_SYM;
+  if (sym && rb < kb) return;
+  int seg, k0, klim;
+  oz_block(s, kb, &seg, &k0, &klim);
+  __shared__ double t[64][65];
+  oz_stage(s, rb * 64, k0, klim, t);
+  __syncthreads();
+  const int tid = threadIdx.x;
+  unsigned long long *rm = rmax + (int64_t)seg * s.rows;
+  if (tid < 64) {  // row maxima
+    double m = 0.0;
+    for (int k = 0; k < 64; ++k) m = fmax(m, fabs(t[tid][k]));
+    const int r = rb * 64 + tid;
+    if (r < s.rows && m > 0.0) atomicMax(rm + r, (unsigned long long)__double_as_longlong(m));
+  } else if (sym && rb > kb && tid < 128) {  // column maxima (the mirrored rows)
+    const int k = tid - 64;
+    double m = 0.0;
+    for (int r = 0; r < 64; ++r) m = fmax(m, fabs(t[r][k]));
+    const int rr = kb * 64 + k;
+    if (rr < s.rows && m > 0.0) atomicMax(rm + rr, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// exponent e of a row: its largest |entry| is below 2^e (0 for a zero row)
+__global__ void k_oz_exps(const unsigned long long *rmax, int count, int *ex) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= count) return;
+  const double m = __longlong_as_double((long long)rmax[r]);
+  int e = 0;
+  if (m > 0.0) frexp(m, &e);  // m = f 2^e, f in [0.5, 1)
+  ex[r] = e;
+}
+
+// The digits of 4 consecutive entries of one row, packed 4 to a word per plane.
+__device__ __forceinline__ void oz_digits4(const double *v, int e, int8_t *dst, int64_t plane) {
+  double y[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) y[c] = ldexp(v[c], -e);
+#pragma unroll
+  for (int p = 0; p < kOzS; ++p) {
+    unsigned w = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      y[c] *= 128.0;
+      const double d = trunc(y[c]);
+      y[c] -= d;
+      w |= ((unsigned)(int)d & 0xffu) << (8 * c);
+    }
+    *(unsigned *)(dst + p * plane) = w;
+  }
+}
+
+// planes[p][r][c] = digit p + 1 of the entry of row r at plane column c
+// (zero in the padding).  A symmetric operand stages its lower blocks only
+// and writes each one twice (as rows and, mirrored, as columns).
+__global__ __launch_bounds__(256) void k_oz_slice(OzSrc s, const int *ex, int8_t *planes) {
+  const int kb = blockIdx.x, rb = blockIdx.y;
+  const bool sym = !s.isB && s.op == A_SYM;
+  if (sym && rb < kb) return;
+  int seg, k0, klim;
+  oz_block(s, kb, &seg, &k0, &klim);
+  __shared__ double t[64][65];
+  oz_stage(s, rb * 64, k0, klim, t);
+  __syncthreads();
+  const int64_t plane = (int64_t)s.rows * s.Kp;
+  const int *exs = ex + (int64_t)seg * s.rows;
+  const int tid = threadIdx.x;
+  const int passes = (sym && rb > kb) ? 2 : 1;
+  for (int pass = 0; pass < passes; ++pass) {
+    const int R0 = pass ? kb * 64 : rb * 64, C0 = pass ? rb * 64 : kb * 64;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int task = tid + 256 * i;  // 64 rows x 16 groups of 4 entries
+      const int rl = task >> 4, g = task & 15;
+      const int r = R0 + rl;
+      if (r >= s.rows) continue;
+      double v[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[c] = pass ? t[4 * g + c][rl] : t[rl][4 * g + c];
+      oz_digits4(v, exs[r], planes + (int64_t)r * s.Kp + C0 + 4 * g, plane);
+    }
+  }
+}
+
+struct OzDesc {
+  const int8_t *PA, *PB;   // planes of op(A) (M x Kp each) and op(B) (N x Kp each)
+  const int *ea, *eb;      // exponents: ea[seg M + row], eb[seg N + col]
+  int M, N, Kp, L0;        // plane columns, and where segment 1 starts
+  int kchunk;              // k range of one blockIdx.z (multiple of 64)
+  double *C;
+  int64_t ldc;
+  double alpha, beta;
+  double *part;            // split-k partials (E_PART)
+  int c0, c1;              // SYR2K column range
+  const int *abort;
+};
+
+// 64 x 64 output tile, 4 waves as 2 x 2 (32 x 32 each: 2 x 2 blocks of 16 x 16)
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm_oz(OzDesc d) {
+  if (d.abort && *d.abort != 0) return;
+  int i0, j0, kbeg, kend;
+  if (EPI == E_SYR2K) {
+    const int I = blockIdx.x, J = blockIdx.y;
+    if ((I + 1) * 64 - 1 < J * 64) return;  // tile entirely above the diagonal
+    i0 = d.c0 + I * 64;
+    j0 = d.c0 + J * 64;
+    kbeg = 0;
+    kend = d.Kp;
+  } else {
+    i0 = blockIdx.x * 64;
+    j0 = blockIdx.y * 64;
+    kbeg = blockIdx.z * d.kchunk;
+    kend = min(d.Kp, kbeg + d.kchunk);
+  }
+  const int Nlim = (EPI == E_SYR2K) ? d.c1 : d.N;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int64_t planeA = (int64_t)d.M * d.Kp, planeB = (int64_t)d.N * d.Kp;
+  // the rows / columns whose operand fragments this lane loads, and those of
+  // its results (clamped: indices beyond the matrix read row 0 / the last
+  // exponent and their results are dropped)
+  int ra[2], cb[2], er[2][4], ec[2];
+#pragma unroll
+  for (int f = 0; f < 2; ++f) {
+    const int r = i0 + wm * 32 + f * 16 + (lane & 15);
+    const int c = j0 + wn * 32 + f * 16 + (lane & 15);
+    ra[f] = r < d.M ? r : 0;
+    cb[f] = c < d.N ? c : 0;
+    ec[f] = min(c, d.N - 1);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) er[f][e] = min(i0 + wm * 32 + f * 16 + 4 * (lane >> 4) + e, d.M - 1);
+  }
+  const int kl = 16 * (lane >> 4);
+  double acc64[2][2][4];
+  v4i acc[kOzS][2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc64[a][b][e] = 0.0;
+#pragma unroll
+      for (int t = 0; t < kOzS; ++t) acc[t][a][b] = v4i{0, 0, 0, 0};
+    }
+  // int32 sums -> FP64, scaled by the segment's row and column exponents
+  auto fold = [&](int seg) {
+    const int *ea = d.ea + (int64_t)seg * d.M, *eb = d.eb + (int64_t)seg * d.N;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int xb = eb[ec[b]];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          double s = 0.0;
+#pragma unroll
+          for (int t = kOzS - 1; t >= 0; --t)  // pair sum p + q = t + 2, smallest first
+            s += (double)acc[t][a][b][e] * ldexp(1.0, -7 * (t + 2));
+          acc64[a][b][e] += ldexp(s, ea[er[a][e]] + xb);
+        }
+#pragma unroll
+        for (int t = 0; t < kOzS; ++t) acc[t][a][b] = v4i{0, 0, 0, 0};
+      }
+  };
+  int seg = kbeg >= d.L0 ? 1 : 0;
+  int since = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += 64) {
+    v4i bq[kOzS][2];
+#pragma unroll
+    for (int q = 0; q < kOzS; ++q)
+#pragma unroll
+      for (int f = 0; f < 2; ++f)
+        bq[q][f] = *(const v4i *)(d.PB + q * planeB + (int64_t)cb[f] * d.Kp + k0 + kl);
+#pragma unroll
+    for (int p = 0; p < kOzS; ++p) {
+      v4i ap[2];
+#pragma unroll
+      for (int f = 0; f < 2; ++f)
+        ap[f] = *(const v4i *)(d.PA + p * planeA + (int64_t)ra[f] * d.Kp + k0 + kl);
+#pragma unroll
+      for (int q = 0; q + p < kOzS; ++q)  // pairs with (p+1) + (q+1) <= S + 1
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[p + q][a][b] =
+                __builtin_amdgcn_mfma_i32_16x16x64_i8(ap[a], bq[q][b], acc[p + q][a][b], 0, 0, 0);
+    }
+    since += 64;
+    const bool seg_end = (k0 + 64 == d.L0);
+    if (seg_end || since >= kOzKF) {
+      fold(seg);
+      since = 0;
+      if (seg_end) seg = 1;
+    }
+  }
+  if (since > 0) fold(seg);
+  // element e of block (a, b) is row 4 (lane / 16) + e, column lane % 16
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = i0 + wm * 32 + a * 16 + 4 * (lane >> 4) + e;
+        const int col = j0 + wn * 32 + b * 16 + (lane & 15);
+        bool in = row < d.M && col < Nlim;
+        if (EPI == E_SYR2K) in = in && row >= col;
+        if (!in) continue;
+        const double v = acc64[a][b][e];
+        if (EPI == E_AXPBY) {
+          double *c = d.C + row + (int64_t)col * d.ldc;
+          *c = (d.beta == 0.0) ? d.alpha * v : d.alpha * v + d.beta * (*c);
+        } else if (EPI == E_PART) {
+          d.part[(int64_t)blockIdx.z * d.M * d.N + row + (int64_t)col * d.M] = v;
+        } else {
+          double *c = d.C + row + (int64_t)col * d.ldc;
+          *c = *c - v;
+        }
+      }
+}
+
+int oz_plane_cols(int K, int ks, int *L0) {
+  if (ks <= 0 || ks >= K) ks = K;
+  *L0 = (ks + 63) / 64 * 64;
+  return *L0 + (K - ks + 63) / 64 * 64;
+}
+
+int oz_slice(const double *X, int64_t ld, int op, int rows, int K, int ks, int rot, int isB,
+             unsigned long long *rmax, int *ex, int8_t *planes, hipStream_t s) {
+  if (rows <= 0) return 0;
+  if (ks <= 0 || ks >= K) ks = K;
+  int L0 = 0;
+  const int Kp = oz_plane_cols(K, ks, &L0);
+  if (op == A_SYM && !isB && ks != K) return BANDRED_ERR_UNSUPPORTED;
+  OzSrc src{X, ld, op, isB, rows, K, rot, ks, L0, Kp};
+  const int nseg = (ks < K) ? 2 : 1;
+  int rc = launch_fill_u32((unsigned *)rmax, 2 * (int64_t)nseg * rows, 0u, s);
+  if (rc) return rc;
+  const dim3 grid(Kp / 64, (rows + 63) / 64);
+  hipLaunchKernelGGL(k_oz_rowmax, grid, dim3(256), 0, s, src, rmax);
+  BR_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_oz_exps, dim3((nseg * rows + 255) / 256), dim3(256), 0, s,
+                     (const unsigned long long *)rmax, nseg * rows, ex);
+  BR_HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_oz_slice, grid, dim3(256), 0, s, src, (const int *)ex, planes);
+  BR_HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
+int oz_gemm(int epi, const int8_t *PA, const int8_t *PB, const int *ea, const int *eb, int M,
+            int N, int Kp, int L0, int ksplit, int kchunk, double *C, int64_t ldc, double alpha,
+            double beta, double *part, int c0, int c1, const int *abort, hipStream_t s) {
+  OzDesc d{};
+  d.PA = PA; d.PB = PB; d.ea = ea; d.eb = eb;
+  d.M = M; d.N = N; d.Kp = Kp; d.L0 = L0; d.kchunk = kchunk;
+  d.C = C; d.ldc = ldc; d.alpha = alpha; d.beta = beta; d.part = part;
+  d.c0 = c0; d.c1 = c1; d.abort = abort;
+  if (epi == E_SYR2K) {
+    const int rows = M - c0, cols = c1 - c0;
+    if (rows <= 0 || cols <= 0) return 0;
+    hipLaunchKernelGGL(k_gemm_oz<E_SYR2K>, dim3((rows + 63) / 64, (cols + 63) / 64), dim3(256), 0,
+                       s, d);
+  } else if (epi == E_PART) {
+    hipLaunchKernelGGL(k_gemm_oz<E_PART>, dim3((M + 63) / 64, (N + 63) / 64, ksplit), dim3(256),
+                       0, s, d);
+  } else {
+    hipLaunchKernelGGL(k_gemm_oz<E_AXPBY>, dim3((M + 63) / 64, (N + 63) / 64, 1), dim3(256), 0,
+                       s, d);
+  }
+  BR_HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
+}  // namespace br
