@@ -57,14 +57,15 @@ typedef enum {
                                  MFMA with FP32 accumulation, summed in FP64 */
   BANDRED_INT8_SPLIT_UPDATE = 3 /* exact split (error-free slicing): each row of the left
                                  operand and column of the right one scaled by a power of
-                                 two and cut into 8 int8 digits of 7 bits; the 36 digit
-                                 products of order <= 9 run on int8 MFMA with exact int32
-                                 sums and are combined in FP64.  Per term of the inner
-                                 dimension K the dropped part is below 2^-52 of the
-                                 product of the row and column scales, under the
-                                 worst-case error of an FP64 dot product.  Not in the paper (which is
-                                 FP64 throughout).  Work space grows by about
-                                 8 (n + 2w) n bytes (SY2SB; m and n for GE2GB) */
+                                 two and cut into 7 signed base-256 int8 digits; the 28
+                                 digit products of order <= 8 run on int8 MFMA with exact
+                                 int32 sums and are combined in FP64.  Per term of the
+                                 inner dimension the error is below 2^-49 of the product
+                                 of the row's and the column's largest entries, under the
+                                 worst-case error of an FP64 dot product.  Rank-2k updates
+                                 scale their two halves apart.  Not in the paper (which
+                                 is FP64 throughout).  Work space grows by about
+                                 7 (n + 2w) n bytes (SY2SB; m and n for GE2GB) */
 } bandred_prec_t;
 
 /* Optional knobs for the _ex entry points (pass NULL for defaults). */

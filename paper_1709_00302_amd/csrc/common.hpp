@@ -19,9 +19,9 @@ constexpr int kBK = 16;         // k-depth of one LDS stage of the GEMM kernels
 // Trailing-update arithmetic (matches bandred_prec_t).
 enum Prec { P_F64 = 0, P_F32 = 1, P_SPLIT = 2, P_OZ = 3 };
 
-// exact-split form (ozaki.hip): int8 digits per operand entry, and the k
-// range after which the int32 accumulators are folded into FP64
-constexpr int kOzS = 8;
+// exact-split form (ozaki.hip): int8 digits (base 256) per operand entry,
+// and the k range after which the int32 accumulators are folded into FP64
+constexpr int kOzS = 7;
 constexpr int kOzKF = 2048;
 
 // Operand access patterns of the GEMM kernels.

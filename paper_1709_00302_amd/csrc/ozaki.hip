@@ -8,24 +8,30 @@
 // The inner dimension is cut into one or two segments (the rank-2k updates
 // take [W | V] [V | W]^T as two: their halves differ in scale by the norm of
 // the matrix).  In segment s, row i of op(A) is scaled by 2^-e_si so that its
-// largest entry is below 1 in magnitude, and written as kOzS digits of 7 bits:
-//     a 2^-e_si = sum_{p=1..S} d_p 128^-p + r,   d_p in [-127, 127], |r| < 128^-S
-// (each digit the truncated integer part of the running remainder times 128,
-// all exact in FP64); column j of op(B) likewise with 2^-f_sj.  Then
-//     C_ij = sum_s 2^(e_si + f_sj) sum_t 128^-t sum_{p+q=t} sum_{k in s} d^A_p(i,k) d^B_q(k,j),
-// where the pairs with p + q > S + 1 are dropped.  Pairs of equal t share one
-// int32 accumulator, which the kernel folds into FP64 at the end of a segment
-// and every kOzKF terms of k (at most 8 x 2048 x 127^2 < 2^31 in magnitude,
-// so the int32 sums are exact).  With S = 8, per term of k the dropped pairs
-// (7 of order 10, each below 2^-56, and fewer of higher order) and the two
-// truncation remainders (each below 2^-56) add up to less than 2^-52 of
-// 2^(e_si + f_sj): the error of C_ij is below 2^-52 sum_s K_s 2^(e_si + f_sj),
-// under the worst-case bound of an FP64 dot product of length K.
+// entries are below (127/128)/2 in magnitude, rounded to a multiple of 2^-56
+// (remainder at most 2^-57) and written as kOzS = 7 signed base-256 digits:
+//     a 2^-e_si = sum_{p=1..7} d_p 256^-p + r,   d_p in [-128, 127], |r| <= 2^-57
+// (the integer a 2^(56 - e_si) cut into bytes from the least significant up,
+// each byte taken in [-128, 127] with a carry into the next: every step is
+// exact in FP64, and the bound on the entries keeps the top digit within
+// [-127, 127]); column j of op(B) likewise with 2^-f_sj.  Then
+//     C_ij = sum_s 2^(e_si + f_sj) sum_t 256^-t sum_{p+q=t} sum_{k in s} d^A_p(i,k) d^B_q(k,j),
+// keeping the 28 pairs with p + q <= 8.  Pairs of equal t share one int32
+// accumulator, which the kernel folds into FP64 at the end of a segment and
+// every kOzKF terms of k (at most 7 x 2048 x 128^2 < 2^31 in magnitude, so
+// the int32 sums are exact).  Per term of k the dropped pairs (6 of order 9,
+// each below 2^-58, and fewer of higher order) and the two rounding
+// remainders (together at most 2^-57, the scaled entries being below 1/2)
+// add up to less than 2^-54 of 2^(e_si + f_sj), and 2^e_si is at most
+// 4 (128/127) times the largest entry of the row in the segment: the error of
+// C_ij is below 2^-49 sum_s K_s max_k|a_ik| max_k|b_kj|, under the worst-case
+// bound of an FP64 dot product of length K.
 //
 // Slices are stored as planes: plane p of op(A) is M x Kp int8 with k
 // contiguous (each segment zero padded to a multiple of 64, Kp the sum),
-// plane q of op(B) N x Kp likewise, so that a lane's 16 bytes of an MFMA
-// operand are one 16-byte load.
+// plane q of op(B) N x Kp likewise.  The product kernel stages 64 x 64 blocks
+// of every plane through LDS (double buffered); a lane's 16 bytes of an MFMA
+// operand are one LDS read.
 // v_mfma_i32_16x16x64_i8 (measured on gfx950): lane l supplies A(l % 16,
 // 16 (l / 16) + e) and B(16 (l / 16) + e, l % 16) as bytes e = 0..15 and
 // receives D(4 (l / 16) + e, l % 16) in element e.
@@ -100,48 +106,72 @@ __global__ __launch_bounds__(256) void k_oz_rowmax(OzSrc s, unsigned long long *
   __shared__ double t[64][65];
   oz_stage(s, rb * 64, k0, klim, t);
   __syncthreads();
-  const int tid = threadIdx.x;
+  // four adjacent lanes per row (per column): a quarter each, then combined
+  const int tid = threadIdx.x, x = tid >> 2, q = tid & 3;
   unsigned long long *rm = rmax + (int64_t)seg * s.rows;
-  if (tid < 64) {  // row maxima
-    double m = 0.0;
-    for (int k = 0; k < 64; ++k) m = fmax(m, fabs(t[tid][k]));
-    const int r = rb * 64 + tid;
-    if (r < s.rows && m > 0.0) atomicMax(rm + r, (unsigned long long)__double_as_longlong(m));
-  } else if (sym && rb > kb && tid < 128) {  // column maxima (the mirrored rows)
-    const int k = tid - 64;
-    double m = 0.0;
-    for (int r = 0; r < 64; ++r) m = fmax(m, fabs(t[r][k]));
-    const int rr = kb * 64 + k;
-    if (rr < s.rows && m > 0.0) atomicMax(rm + rr, (unsigned long long)__double_as_longlong(m));
+  double m = 0.0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) m = fmax(m, fabs(t[x][16 * q + k]));
+  m = fmax(m, __shfl_xor(m, 1));
+  m = fmax(m, __shfl_xor(m, 2));
+  const int r = rb * 64 + x;
+  if (q == 0 && r < s.rows && m > 0.0)
+    atomicMax(rm + r, (unsigned long long)__double_as_longlong(m));
+  if (sym && rb > kb) {  // column maxima (the mirrored rows)
+    double c = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) c = fmax(c, fabs(t[16 * q + i][x]));
+    c = fmax(c, __shfl_xor(c, 1));
+    c = fmax(c, __shfl_xor(c, 2));
+    const int rr = kb * 64 + x;
+    if (q == 0 && rr < s.rows && c > 0.0)
+      atomicMax(rm + rr, (unsigned long long)__double_as_longlong(c));
   }
 }
 
-// exponent e of a row: its largest |entry| is below 2^e (0 for a zero row)
+// exponent e of a row: its entries are below (127/128) 2^(e - 1) in
+// magnitude (0 for a zero row)
 __global__ void k_oz_exps(const unsigned long long *rmax, int count, int *ex) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= count) return;
   const double m = __longlong_as_double((long long)rmax[r]);
   int e = 0;
-  if (m > 0.0) frexp(m, &e);  // m = f 2^e, f in [0.5, 1)
+  if (m > 0.0) {
+    const double f = frexp(m, &e);  // m = f 2^e, f in [0.5, 1)
+    if (f >= 127.0 / 128.0) ++e;    // then m < (127/128) 2^e
+    ++e;
+  }
   ex[r] = e;
 }
 
-// The digits of 4 consecutive entries of one row, packed 4 to a word per plane.
+// The digits of 4 consecutive entries of one row, packed 4 to a word per
+// plane.  With Y = rint(a 2^(56 - e)) (|Y| < 127 2^48) and C the integer with
+// seven bytes 0x80, Z = Y + C lies in [0, 2^56); byte k of Z less 128 is the
+// digit of weight 256^k (that subtraction makes the carries: Y = Z - C), and
+// as an int8 it is the byte with its top bit flipped.  Y is assembled from
+// two exact 32-bit conversions.
 __device__ __forceinline__ void oz_digits4(const double *v, int e, int8_t *dst, int64_t plane) {
-  double y[4];
+  unsigned zl[4], zh[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) y[c] = ldexp(v[c], -e);
+  for (int c = 0; c < 4; ++c) {
+    const double r = rint(ldexp(v[c], 56 - e));
+    const double h = floor(r * 0x1p-32);
+    const double l = fma(-h, 0x1p32, r);  // exact, in [0, 2^32)
+    const uint64_t Y = ((uint64_t)(int64_t)(int)h << 32) + (uint64_t)(unsigned)l;
+    const uint64_t Z = Y + 0x0080808080808080ull;
+    zl[c] = (unsigned)Z;
+    zh[c] = (unsigned)(Z >> 32);
+  }
 #pragma unroll
-  for (int p = 0; p < kOzS; ++p) {
+  for (int p = 0; p < kOzS; ++p) {  // plane p holds the digit of weight 256^(6 - p)
+    const int k = kOzS - 1 - p;
     unsigned w = 0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      y[c] *= 128.0;
-      const double d = trunc(y[c]);
-      y[c] -= d;
-      w |= ((unsigned)(int)d & 0xffu) << (8 * c);
+      const unsigned src = k < 4 ? zl[c] : zh[c];
+      w |= ((src >> (8 * (k & 3))) & 0xffu) << (8 * c);
     }
-    *(unsigned *)(dst + p * plane) = w;
+    *(unsigned *)(dst + p * plane) = w ^ 0x80808080u;
   }
 }
 
@@ -187,46 +217,85 @@ struct OzDesc {
   double alpha, beta;
   double *part;            // split-k partials (E_PART)
   int c0, c1;              // SYR2K column range
+  int nI, nJ, nZ;          // tiles: row blocks, column blocks, k chunks
   const int *abort;
 };
+
+// LDS image of one plane's 64 x 64 block: row r, 16-byte chunk c at
+// 64 r + 16 (c ^ ((r / 4) mod 4)), so that the 16 rows one MFMA operand read
+// touches fall on distinct banks
+__device__ __forceinline__ int oz_swz(int r, int c) { return r * 64 + ((c ^ ((r >> 2) & 3)) << 4); }
+constexpr int kOzBlk = 64 * 64;             // bytes of one plane's block
+constexpr int kOzStage = 2 * kOzS * kOzBlk; // both operands, all planes
 
 // 64 x 64 output tile, 4 waves as 2 x 2 (32 x 32 each: 2 x 2 blocks of 16 x 16)
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm_oz(OzDesc d) {
+  __shared__ __attribute__((aligned(16))) int8_t lds[2 * kOzStage];
   if (d.abort && *d.abort != 0) return;
-  int i0, j0, kbeg, kend;
+  // one tile per workgroup: the SYR2K enumerates only the tiles that reach
+  // the lower triangle (column J holds row blocks J .. nI-1), the others
+  // every (row block, column block, k chunk) with the row block fastest
+  const int T = blockIdx.x;
+  int i0, j0, kbeg, kend, z = 0;
   if (EPI == E_SYR2K) {
-    const int I = blockIdx.x, J = blockIdx.y;
-    if ((I + 1) * 64 - 1 < J * 64) return;  // tile entirely above the diagonal
+    // J: the largest column with S(J) = J nI - J (J - 1) / 2 <= T
+    const double b2 = d.nI + 0.5;
+    int J = (int)(b2 - sqrt(b2 * b2 - 2.0 * T));
+    J = max(0, min(J, d.nJ - 1));
+    auto S = [&](int x) { return x * d.nI - x * (x - 1) / 2; };
+    while (J > 0 && S(J) > T) --J;
+    while (J + 1 < d.nJ && S(J + 1) <= T) ++J;
+    const int I = J + (T - S(J));
     i0 = d.c0 + I * 64;
     j0 = d.c0 + J * 64;
     kbeg = 0;
     kend = d.Kp;
   } else {
-    i0 = blockIdx.x * 64;
-    j0 = blockIdx.y * 64;
-    kbeg = blockIdx.z * d.kchunk;
+    const int I = T % d.nI, J = (T / d.nI) % d.nJ;
+    z = T / (d.nI * d.nJ);
+    i0 = I * 64;
+    j0 = J * 64;
+    kbeg = z * d.kchunk;
     kend = min(d.Kp, kbeg + d.kchunk);
   }
   const int Nlim = (EPI == E_SYR2K) ? d.c1 : d.N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const int64_t planeA = (int64_t)d.M * d.Kp, planeB = (int64_t)d.N * d.Kp;
-  // the rows / columns whose operand fragments this lane loads, and those of
-  // its results (clamped: indices beyond the matrix read row 0 / the last
-  // exponent and their results are dropped)
-  int ra[2], cb[2], er[2][4], ec[2];
+  // staging, global -> LDS without registers: wave w moves rows 16 w ..
+  // 16 w + 15 of every plane's block of both operands, 1 KB per instruction
+  // written lane-contiguously; lane L lands at 16 L = 64 (L / 4) + 16 (L % 4)
+  // of the rows' image, which under the swizzle holds chunk
+  // (L % 4) ^ ((row / 4) % 4) of row 16 w + L / 4.  Rows beyond the matrix
+  // read row 0; their results are dropped.
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  const int sr = 16 * wv + (lane >> 2);
+  const int sc = (lane & 3) ^ ((sr >> 2) & 3);
+  typedef __attribute__((address_space(1))) const void gvoid;
+  typedef __attribute__((address_space(3))) void lvoid;
+  const int8_t *gA = d.PA + (int64_t)(i0 + sr < d.M ? i0 + sr : 0) * d.Kp + 16 * sc;
+  const int8_t *gB = d.PB + (int64_t)(j0 + sr < d.N ? j0 + sr : 0) * d.Kp + 16 * sc;
+  auto issue_stage = [&](int k0, int buf) {
+    int8_t *base = lds + buf * kOzStage + wv * 1024;
+#pragma unroll
+    for (int p = 0; p < kOzS; ++p) {
+      __builtin_amdgcn_global_load_lds((gvoid *)(gA + p * planeA + k0), (lvoid *)(base + p * kOzBlk),
+                                       16, 0, 0);
+      __builtin_amdgcn_global_load_lds((gvoid *)(gB + p * planeB + k0),
+                                       (lvoid *)(base + (kOzS + p) * kOzBlk), 16, 0, 0);
+    }
+  };
+  // the lane's operand rows in the block, and its result rows / columns
+  int fa[2], fb[2], er[2][4], ec[2];
 #pragma unroll
   for (int f = 0; f < 2; ++f) {
-    const int r = i0 + wm * 32 + f * 16 + (lane & 15);
-    const int c = j0 + wn * 32 + f * 16 + (lane & 15);
-    ra[f] = r < d.M ? r : 0;
-    cb[f] = c < d.N ? c : 0;
-    ec[f] = min(c, d.N - 1);
+    fa[f] = oz_swz(wm * 32 + f * 16 + (lane & 15), lane >> 4);
+    fb[f] = oz_swz(wn * 32 + f * 16 + (lane & 15), lane >> 4);
+    ec[f] = min(j0 + wn * 32 + f * 16 + (lane & 15), d.N - 1);
 #pragma unroll
     for (int e = 0; e < 4; ++e) er[f][e] = min(i0 + wm * 32 + f * 16 + 4 * (lane >> 4) + e, d.M - 1);
   }
-  const int kl = 16 * (lane >> 4);
   double acc64[2][2][4];
   v4i acc[kOzS][2][2];
 #pragma unroll
@@ -250,47 +319,57 @@ __global__ __launch_bounds__(256) void k_gemm_oz(OzDesc d) {
         for (int e = 0; e < 4; ++e) {
           double s = 0.0;
 #pragma unroll
-          for (int t = kOzS - 1; t >= 0; --t)  // pair sum p + q = t + 2, smallest first
-            s += (double)acc[t][a][b][e] * ldexp(1.0, -7 * (t + 2));
+          for (int t = kOzS - 1; t >= 0; --t)  // pair order t + 2, smallest first
+            s += (double)acc[t][a][b][e] * ldexp(1.0, -8 * (t + 2));
           acc64[a][b][e] += ldexp(s, ea[er[a][e]] + xb);
         }
 #pragma unroll
         for (int t = 0; t < kOzS; ++t) acc[t][a][b] = v4i{0, 0, 0, 0};
       }
   };
-  int seg = kbeg >= d.L0 ? 1 : 0;
-  int since = 0;
-  for (int k0 = kbeg; k0 < kend; k0 += 64) {
-    v4i bq[kOzS][2];
-#pragma unroll
-    for (int q = 0; q < kOzS; ++q)
-#pragma unroll
-      for (int f = 0; f < 2; ++f)
-        bq[q][f] = *(const v4i *)(d.PB + q * planeB + (int64_t)cb[f] * d.Kp + k0 + kl);
-#pragma unroll
-    for (int p = 0; p < kOzS; ++p) {
-      v4i ap[2];
-#pragma unroll
-      for (int f = 0; f < 2; ++f)
-        ap[f] = *(const v4i *)(d.PA + p * planeA + (int64_t)ra[f] * d.Kp + k0 + kl);
-#pragma unroll
-      for (int q = 0; q + p < kOzS; ++q)  // pairs with (p+1) + (q+1) <= S + 1
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b)
-            acc[p + q][a][b] =
-                __builtin_amdgcn_mfma_i32_16x16x64_i8(ap[a], bq[q][b], acc[p + q][a][b], 0, 0, 0);
-    }
-    since += 64;
-    const bool seg_end = (k0 + 64 == d.L0);
-    if (seg_end || since >= kOzKF) {
-      fold(seg);
-      since = 0;
-      if (seg_end) seg = 1;
-    }
+  const int nst = (kend - kbeg) / 64;
+  if (nst > 0) {
+    issue_stage(kbeg, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
   }
-  if (since > 0) fold(seg);
+  // runs of stages between folds: a run ends at the end of a segment or
+  // after kOzKF terms of k
+  int st = 0;
+  while (st < nst) {
+    const int k0 = kbeg + 64 * st;
+    const int seg = k0 >= d.L0 ? 1 : 0;
+    int stop = min(nst, st + kOzKF / 64);
+    if (seg == 0) stop = min(stop, (d.L0 - kbeg) / 64);
+    for (; st < stop; ++st) {
+      const int8_t *A = lds + (st & 1) * kOzStage, *B = A + kOzS * kOzBlk;
+      // the next stage into the other buffer (last read before the previous
+      // barrier), in flight during this stage's products
+      if (st + 1 < nst) issue_stage(kbeg + 64 * (st + 1), (st + 1) & 1);
+      v4i bq[kOzS][2];
+#pragma unroll
+      for (int q = 0; q < kOzS; ++q)
+#pragma unroll
+        for (int f = 0; f < 2; ++f) bq[q][f] = *(const v4i *)(B + q * kOzBlk + fb[f]);
+#pragma unroll
+      for (int p = 0; p < kOzS; ++p) {
+        v4i ap[2];
+#pragma unroll
+        for (int f = 0; f < 2; ++f) ap[f] = *(const v4i *)(A + p * kOzBlk + fa[f]);
+#pragma unroll
+        for (int q = 0; q + p < kOzS; ++q)  // pairs with (p+1) + (q+1) <= 8
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+              acc[p + q][a][b] =
+                  __builtin_amdgcn_mfma_i32_16x16x64_i8(ap[a], bq[q][b], acc[p + q][a][b], 0, 0, 0);
+      }
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+    }
+    fold(seg);
+  }
   // element e of block (a, b) is row 4 (lane / 16) + e, column lane % 16
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -308,7 +387,7 @@ __global__ __launch_bounds__(256) void k_gemm_oz(OzDesc d) {
           double *c = d.C + row + (int64_t)col * d.ldc;
           *c = (d.beta == 0.0) ? d.alpha * v : d.alpha * v + d.beta * (*c);
         } else if (EPI == E_PART) {
-          d.part[(int64_t)blockIdx.z * d.M * d.N + row + (int64_t)col * d.M] = v;
+          d.part[(int64_t)z * d.M * d.N + row + (int64_t)col * d.M] = v;
         } else {
           double *c = d.C + row + (int64_t)col * d.ldc;
           *c = *c - v;
@@ -355,15 +434,22 @@ int oz_gemm(int epi, const int8_t *PA, const int8_t *PB, const int *ea, const in
   if (epi == E_SYR2K) {
     const int rows = M - c0, cols = c1 - c0;
     if (rows <= 0 || cols <= 0) return 0;
-    hipLaunchKernelGGL(k_gemm_oz<E_SYR2K>, dim3((rows + 63) / 64, (cols + 63) / 64), dim3(256), 0,
-                       s, d);
-  } else if (epi == E_PART) {
-    hipLaunchKernelGGL(k_gemm_oz<E_PART>, dim3((M + 63) / 64, (N + 63) / 64, ksplit), dim3(256),
-                       0, s, d);
+    d.nI = (rows + 63) / 64; d.nJ = (cols + 63) / 64; d.nZ = 1;
   } else {
-    hipLaunchKernelGGL(k_gemm_oz<E_AXPBY>, dim3((M + 63) / 64, (N + 63) / 64, 1), dim3(256), 0,
-                       s, d);
+    d.nI = (M + 63) / 64; d.nJ = (N + 63) / 64; d.nZ = ksplit;
   }
+  // lower tiles of the SYR2K (cols <= rows: column J has nI - J of them)
+  const int64_t total = (epi == E_SYR2K)
+                            ? (int64_t)d.nJ * d.nI - (int64_t)d.nJ * (d.nJ - 1) / 2
+                            : (int64_t)d.nI * d.nJ * d.nZ;
+  if (total > ((int64_t)1 << 30)) return BANDRED_ERR_UNSUPPORTED;
+  const dim3 grid((unsigned)total);
+  if (epi == E_SYR2K)
+    hipLaunchKernelGGL(k_gemm_oz<E_SYR2K>, grid, dim3(256), 0, s, d);
+  else if (epi == E_PART)
+    hipLaunchKernelGGL(k_gemm_oz<E_PART>, grid, dim3(256), 0, s, d);
+  else
+    hipLaunchKernelGGL(k_gemm_oz<E_AXPBY>, grid, dim3(256), 0, s, d);
   BR_HIP_CHECK(hipGetLastError());
   return 0;
 }

@@ -2,13 +2,14 @@
 (BANDRED_INT8_SPLIT_UPDATE), through the C ABI, against the FP64 oracle.
 
 Every trailing-update product takes its operands as per-row (op(A)) and
-per-column (op(B)) power-of-two scales times 8 int8 digits of 7 bits each,
-multiplies the 36 digit pairs of order <= 9 on the int8 matrix cores with
-exact int32 sums and combines them in FP64.  Per term of the inner dimension
-the dropped part is below 2^-52 of the product of the scales, under the
-worst-case bound of an FP64 dot product; the panels are FP64.  So this form
-is held to the FP64 bars of the FP64 parity tests: band entries against the
-oracle at 1e-14 n max|B|, v and tau at 1e-14 n, backward error 1e-14 n -- and
+per-column (op(B)) power-of-two scales times 7 signed base-256 int8 digits,
+multiplies the 28 digit pairs of order <= 8 on the int8 matrix cores with
+exact int32 sums and combines them in FP64; rank-2k updates scale their two
+halves apart.  Per term of the inner dimension the error is below 2^-49 of the
+product of the row's and the column's largest entries, under the worst-case
+bound of an FP64 dot product; the panels are FP64.  So this form is held to
+the FP64 bars of the FP64 parity tests: band entries against the oracle at
+1e-14 n max|B|, v and tau at 1e-14 n, backward error 1e-14 n -- and
 at full size to the near-FP64 bound 1e-12 n that the FP32-split form misses.
 """
 import numpy as np
