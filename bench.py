@@ -74,9 +74,9 @@ def reduce_fn(br, kind):
     return {"sy": br.sy2sb, "ge": br.ge2gb, "lu": br.ge2gb_lu}[kind]
 
 
-def serial_call(br, A, kind, w, b):
-    """One FP64 reduction without look-ahead: every kernel alone on the GPU."""
-    reduce_fn(br, kind)(A, w, b, prec="fp64", lookahead=False)
+def serial_call(br, A, kind, w, b, prec="fp64"):
+    """One reduction without look-ahead: every kernel alone on the GPU."""
+    reduce_fn(br, kind)(A, w, b, prec=prec, lookahead=False)
 
 
 def serial_roofline(br, A, restore, kind, w, b, workload):
@@ -431,6 +431,9 @@ def main():
     ap.add_argument("--serial-only", action="store_true",
                     help="a plain device copy of the matrix (calibrates rocprofv3's FETCH_SIZE "
                          "and WRITE_SIZE counters) and one serial reduction (for rocprofv3 --pmc)")
+    ap.add_argument("--serial-prec", default="fp64",
+                    choices=["fp64", "fp32", "split32", "int8split"],
+                    help="trailing-update form of the --serial-only reduction")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only; this build has no multi-GPU path "
@@ -496,10 +499,10 @@ def main():
         del B
         restore()
         torch.cuda.synchronize()
-        serial_call(br, A, kind, w, b)
+        serial_call(br, A, kind, w, b, args.serial_prec)
         torch.cuda.synchronize()
         print(json.dumps({"metric": METRIC, "workload": args.workload, "serial_only": True,
-                          "copy_bytes": 2 * A0.numel() * 8}))
+                          "prec": args.serial_prec, "copy_bytes": 2 * A0.numel() * 8}))
         return
     if args.roofline_only:
         # the serial per-kernel step alone, after one serial warm-up: under
