@@ -52,14 +52,41 @@ __device__ __forceinline__ int sweep_steps(int n, int w, int s) {
   return 1 + (rem > w ? (rem - 1) / w : 0);
 }
 
+constexpr int kS2G = kS2T / kNbMax;  // thread groups sharing one matrix-vector product
+
 struct S2Lds {
   double blk[kNbMax * kS2LD];  // one block of the step, row-major blk[r * kS2LD + c]
   double v[kNbMax];
   double p[kNbMax];
+  double part[kS2G][kNbMax];   // partial sums of the matrix-vector products
   double red[kS2T / 64];
   int go;
   int sweep;
 };
+
+// out[x] = scale * sum_y M(x, y) v[y] for x < nx, y < ny, with M(x, y) =
+// blk[x * kS2LD + y] (rows, trans = 0) or blk[y * kS2LD + x] (columns,
+// trans = 1): kS2G groups of kNbMax threads each take a quarter of y, then
+// the partial sums are added.  Ends with a barrier.
+__device__ __forceinline__ void blk_matvec(S2Lds &sh, int trans, int nx, int ny, double scale,
+                                           double *out) {
+  const int g = threadIdx.x / kNbMax, x = threadIdx.x % kNbMax;
+  const int per = (ny + kS2G - 1) / kS2G, y0 = g * per, y1 = min(ny, y0 + per);
+  if (x < nx) {
+    double acc = 0.0;
+    for (int y = y0; y < y1; ++y)
+      acc += (trans ? sh.blk[y * kS2LD + x] : sh.blk[x * kS2LD + y]) * sh.v[y];
+    sh.part[g][x] = acc;
+  }
+  __syncthreads();
+  if (threadIdx.x < nx) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < kS2G; ++i) t += sh.part[i][threadIdx.x];
+    out[threadIdx.x] = scale * t;
+  }
+  __syncthreads();
+}
 
 __device__ __forceinline__ double block_sum(double x, double *red) {
   // all threads of the workgroup; result in every thread
@@ -140,7 +167,14 @@ __device__ __forceinline__ void bst(double *p, double v) {
 // one step (s, k) of the bulge chasing.  Every block the step touches is
 // brought into LDS with coalesced loads (a column of a block is a contiguous
 // piece of a band-store column), updated there and written back.
-__device__ void sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s, int k) {
+// kept: blk holds the block below of step k - 1 of this sweep as it was
+// written back (rows rx .., columns cx ..): this step's column and bulge
+// block, which no other sweep changes in between (the earlier sweep's steps
+// that meet them finished before step k - 1 began, the later ones start
+// below row rx + w)
+// Returns whether the step left its own block below in blk (false when it
+// ends early: a trivial reflector, or no block below).
+__device__ bool sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s, int k, bool kept) {
   const int n = d.n, w = d.w, tid = threadIdx.x;
   const int64_t ld = d.ldab;
   double *AB = d.AB;
@@ -157,16 +191,17 @@ __device__ void sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s, int k) {
     rx = s + 1 + k * w;
     L = min(w, n - rx);
   }
-  if (L < 2) return;
+  if (L < 2) return false;
+  double *blk = sh.blk;
   // (1) the reflector that annihilates column cx below row rx
   double x = 0.0;
   if (tid < L) {
-    x = get(rx + tid, cx);
+    x = kept ? blk[tid * kS2LD] : get(rx + tid, cx);
     sh.v[tid] = x;
   }
   const double sig2 = block_sum(tid >= 1 && tid < L ? x * x : 0.0, sh.red);
   const double alpha = sh.v[0];
-  if (sig2 == 0.0) return;  // H = I
+  if (sig2 == 0.0) return false;  // H = I
   const double nrm = sqrt(alpha * alpha + sig2);
   const double beta = (alpha < 0.0) ? nrm : -nrm;
   const double tau = (beta - alpha) / beta;
@@ -177,22 +212,36 @@ __device__ void sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s, int k) {
     put(rx + tid, cx, (tid == 0) ? beta : 0.0);
   }
   __syncthreads();
-  double *blk = sh.blk;
   // (2) the rest of the bulge block, rows rx .. rx+L-1, columns cx+1 ..
-  //     cx+w-1, from the left: blk[t][j] = B(rx + t, cx + 1 + j)
+  //     cx+w-1, from the left: B(rx + t, cx + 1 + j) = blk[t][j + o] with
+  //     o = 1 for the kept block (its column 0 is column cx), else 0
   if (k >= 1) {
-    const int nc = w - 1;
-    stage_in(L, nc, [&](int t, int j) { return get(rx + t, cx + 1 + j); },
-             [&](int t, int j, double a) { blk[t * kS2LD + j] = a; });
-    __syncthreads();
-    if (tid < nc) {  // z_j = v^T blk(:, j)
-      double z = 0.0;
-      for (int t = 0; t < L; ++t) z += sh.v[t] * blk[t * kS2LD + tid];
-      sh.p[tid] = tau * z;
+    const int nc = w - 1, o = kept ? 1 : 0;
+    if (!kept) {
+      stage_in(L, nc, [&](int t, int j) { return get(rx + t, cx + 1 + j); },
+               [&](int t, int j, double a) { blk[t * kS2LD + j] = a; });
+      __syncthreads();
     }
-    __syncthreads();
+    // z_j = tau v^T blk(:, j): the columns o .. o + nc - 1 of blk
+    {
+      const int g = tid / kNbMax, xj = tid % kNbMax;
+      const int per = (L + kS2G - 1) / kS2G, t0 = g * per, t1 = min(L, t0 + per);
+      if (xj < nc) {
+        double z = 0.0;
+        for (int t = t0; t < t1; ++t) z += sh.v[t] * blk[t * kS2LD + xj + o];
+        sh.part[g][xj] = z;
+      }
+      __syncthreads();
+      if (tid < nc) {
+        double z = 0.0;
+#pragma unroll
+        for (int i = 0; i < kS2G; ++i) z += sh.part[i][tid];
+        sh.p[tid] = tau * z;
+      }
+      __syncthreads();
+    }
     for_block(L, nc, [&](int t, int j) {
-      put(rx + t, cx + 1 + j, blk[t * kS2LD + j] - sh.p[j] * sh.v[t]);
+      put(rx + t, cx + 1 + j, blk[t * kS2LD + j + o] - sh.p[j] * sh.v[t]);
     });
     __syncthreads();
   }
@@ -207,11 +256,8 @@ __device__ void sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s, int k) {
              }
            });
   __syncthreads();
-  double pt = 0.0;
-  if (tid < L) {
-    for (int u = 0; u < L; ++u) pt += blk[tid * kS2LD + u] * sh.v[u];
-    pt *= tau;
-  }
+  blk_matvec(sh, 0, L, L, tau, sh.p);  // p = tau D v
+  const double pt = tid < L ? sh.p[tid] : 0.0;
   const double pv = block_sum(tid < L ? pt * sh.v[tid] : 0.0, sh.red);
   const double Kc = 0.5 * tau * pv;
   if (tid < L) sh.p[tid] = pt - Kc * sh.v[tid];  // q
@@ -228,16 +274,17 @@ __device__ void sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s, int k) {
     stage_in(m2, L, [&](int i, int u) { return get(r2 + i, rx + u); },
              [&](int i, int u, double a) { blk[i * kS2LD + u] = a; });
     __syncthreads();
-    if (tid < m2) {
-      double y = 0.0;
-      for (int u = 0; u < L; ++u) y += blk[tid * kS2LD + u] * sh.v[u];
-      sh.p[tid] = tau * y;
-    }
-    __syncthreads();
+    blk_matvec(sh, 0, m2, L, tau, sh.p);  // y = tau B v
+    // updated in place and written back; the block stays in LDS for the
+    // next step of this sweep
     for_block(m2, L, [&](int i, int u) {
-      put(r2 + i, rx + u, blk[i * kS2LD + u] - sh.p[i] * sh.v[u]);
+      const double a = blk[i * kS2LD + u] - sh.p[i] * sh.v[u];
+      blk[i * kS2LD + u] = a;
+      put(r2 + i, rx + u, a);
     });
+    return true;
   }
+  return false;
 }
 
 __device__ __forceinline__ long long s2_ticks() { return (long long)wall_clock64(); }
@@ -253,6 +300,7 @@ __global__ __launch_bounds__(kS2T) void k_sb2st(Sb2stDesc d) {
     if (s >= d.nsweeps) return;
     const int K = sweep_steps(d.n, d.w, s);
     const int Kp = (s > 0) ? sweep_steps(d.n, d.w, s - 1) : 0;
+    bool kept = false;  // blk holds the block below of the previous step
     for (int k = 0; k < K; ++k) {
       if (s > 0) {
         if (tid == 0) {
@@ -283,7 +331,7 @@ __global__ __launch_bounds__(kS2T) void k_sb2st(Sb2stDesc d) {
         __syncthreads();
         if (!sh.go) return;
       }
-      sb2st_step(d, sh, s, k);
+      kept = sb2st_step(d, sh, s, k, kept && k >= 1);
       // publish: every thread's stores, then the progress word
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __syncthreads();
