@@ -78,7 +78,19 @@ typedef struct {
                          per-column kernel as fallback for rank-deficient panels and
                          panels with a column that is zero below its diagonal;
                          1: per-column Householder kernel only */
-  int reserved[5];    /* must be zero */
+  int update_chunks;  /* the split of the chip between a look-ahead panel and the update
+                         beside it: an update that runs beside a panel is issued as at most
+                         this many launches (1..8), between which CUs drain and a waiting
+                         panel kernel takes one; each launch keeps at least two rounds of
+                         resident workgroups.  0 (default): 3 for GEMM updates, 2 for the
+                         SYR2K, or the autotuner's choice when b = 0 (bandred_tune) */
+  int update_lds_cap; /* 1: those launches reserve 20 KB of extra LDS per workgroup (one
+                         128 x 128 update workgroup per CU, the rest of the CU left to the
+                         panel); 2: never; 0 (default): when the update has at most 8192
+                         rows, or the autotuner's choice when b = 0.  Neither knob changes
+                         any result bit: every element is still computed by one tile in the
+                         same k order */
+  int reserved[3];    /* must be zero */
 } bandred_opts_t;
 
 /* Symmetric A (n x n) to symmetric band form, bandwidth w, block size b
@@ -251,11 +263,15 @@ BANDRED_API int bandred_sy2sb_batched(int64_t count, const int64_t *n, int64_t w
                           double *const *A, const int64_t *lda,
                           double *const *tau, int prec, void *stream);
 
-/* Block-size autotuner (Sec. 4.2: the best block size depends on n and w,
- * and the paper tunes it per problem in steps of 16).  The reduction's result
- * does not depend on b (up to rounding), so b is picked by timing the
- * reduction of a synthetic matrix of the same shape for every candidate b in
- * {16, 32, ..., min(w, 128)} (b = w when w < 16) on the current device.
+/* Autotuner (Sec. 4.2: the best block size depends on n and w, and the paper
+ * tunes it per problem in steps of 16).  The reduction's result does not
+ * depend on b (up to rounding), so b is picked by timing the reduction of a
+ * synthetic matrix of the same shape for every candidate b in
+ * {16, 32, ..., min(w, 128)} (b = w when w < 16) on the current device; then,
+ * at that b, the split between the look-ahead panel and the update beside it
+ * (bandred_opts_t.update_chunks in {1, 2, 3, 4} and update_lds_cap in {1, 2},
+ * which change no result bit) is picked the same way, and kept when it beats
+ * the default by more than 1%.
  *   kind      0: bandred_sy2sb_ex (m ignored), 1: bandred_ge2gb_ex,
  *             2: bandred_ge2gb_lu                                    (arg 1)
  *   m, n, w   problem shape as in those calls                        (args 2-4)
@@ -267,14 +283,22 @@ BANDRED_API int bandred_sy2sb_batched(int64_t count, const int64_t *n, int64_t w
  *             cache)                                                 (args 8, 9)
  * The choice is cached per device in memory and, if the environment variable
  * BANDRED_TUNE_CACHE names a file, appended to it as one JSON object per line
- * ({"kind": ..., "m": ..., "n": ..., "w": ..., "prec": ..., "b": ..., "ms":
- * {...}}), from which later processes read it back.  Synchronous; allocates
+ * ({"kind": ..., "m": ..., "n": ..., "w": ..., "prec": ..., "b": ..., "chunks": ...,
+ * "cap": ..., "ms": {...}}), from which later processes read it back.  Synchronous; allocates
  * the trial matrix; must not be called under stream capture.  The _ex calls
  * and bandred_ge2gb_lu accept b = 0 to mean "the tuned b" (tuned on first use
  * outside capture; under capture only a cached choice is used, else
  * BANDRED_ERR_UNSUPPORTED). */
 BANDRED_API int bandred_tune(int kind, int64_t m, int64_t n, int64_t w, int prec, int force,
                  int64_t *b_out, double *ms_out, int cap);
+
+/* The autotuner's choice for a problem (kind, m, n, w, prec as for
+ * bandred_tune): block size b (arg 6), update_chunks (arg 7) and
+ * update_lds_cap (arg 8) as bandred_opts_t defines them (HOST pointers, any
+ * may be NULL).  Reads the cache only: returns BANDRED_ERR_UNSUPPORTED when
+ * the problem has not been tuned in this process or in the cache file. */
+BANDRED_API int bandred_tune_result(int kind, int64_t m, int64_t n, int64_t w, int prec,
+                                    int64_t *b, int *update_chunks, int *update_lds_cap);
 
 /* Static description of a status code. */
 BANDRED_API const char *bandred_status_string(int status);

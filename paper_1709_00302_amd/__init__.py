@@ -36,7 +36,8 @@ class BandredError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("lookahead", ctypes.c_int), ("panel_rows", ctypes.c_int),
-                ("panel_method", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
+                ("panel_method", ctypes.c_int), ("update_chunks", ctypes.c_int),
+                ("update_lds_cap", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
 
 
 _i64 = ctypes.c_int64
@@ -74,6 +75,9 @@ def load(path: str = LIB_PATH):
     lib.bandred_tune.argtypes = [ctypes.c_int, _i64, _i64, _i64, ctypes.c_int, ctypes.c_int,
                                  ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double),
                                  ctypes.c_int]
+    lib.bandred_tune_result.argtypes = [ctypes.c_int, _i64, _i64, _i64, ctypes.c_int,
+                                        ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_int)]
     lib.bandred_sb2st.argtypes = [_i64, _i64, _vp, _i64, _vp, _vp, _vp]
     lib.bandred_tridiag_eigvals.argtypes = [_i64, _vp, _vp, _vp, _vp]
     lib.bandred_sy2sb_noalloc.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, ctypes.c_int, _vp]
@@ -94,7 +98,8 @@ def load(path: str = LIB_PATH):
                  "bandred_profile_read",
                  "bandred_status", "bandred_set_wait_limit_us", "bandred_release",
                  "bandred_ge2gb_lu", "bandred_sy2sb_apply_q", "bandred_ge2gb_apply",
-                 "bandred_tune", "bandred_sb2st", "bandred_tridiag_eigvals"):
+                 "bandred_tune", "bandred_tune_result", "bandred_sb2st",
+                 "bandred_tridiag_eigvals"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -155,6 +160,18 @@ def bandred_tune(kind, m, n, w, prec=FP64, force=False):
     ms = {int(buf[2 * i]): buf[2 * i + 1] for i in range(16) if buf[2 * i] > 0}
     return int(b.value), ms
 
+
+
+def bandred_tune_result(kind, m, n, w, prec=FP64):
+    """The cached tuning of a problem: (b, update_chunks, update_lds_cap), or
+    None when it has not been tuned."""
+    b, ch, cap = _i64(0), ctypes.c_int(0), ctypes.c_int(0)
+    rc = load().bandred_tune_result(int(kind), m, n, w, int(prec), ctypes.byref(b),
+                                    ctypes.byref(ch), ctypes.byref(cap))
+    if rc == 3:  # BANDRED_ERR_UNSUPPORTED: not tuned
+        return None
+    _check("bandred_tune_result", rc)
+    return b.value, ch.value, cap.value
 
 def bandred_sb2st(n, w, A, lda, d, e, stream=None) -> int:
     return load().bandred_sb2st(n, w, A, lda, d, e, stream)
@@ -246,7 +263,8 @@ def _check_status(fn: str, handle, check: bool):
 
 
 def sy2sb(A, w: int, b: int | None = None, prec="fp64", lookahead: bool = True,
-          panel_rows: int = 0, panel_method: int = 0, stream=None, tau=None, check: bool = True):
+          panel_rows: int = 0, panel_method: int = 0, stream=None, tau=None, check: bool = True,
+          update_chunks: int = 0, update_lds_cap: int = 0):
     """Reduce the symmetric column-major CUDA tensor ``A`` (lower triangle) to
     band width ``w`` in place; returns tau (device tensor).  With ``check``
     (and outside graph capture) the call waits for the device and raises if
@@ -259,7 +277,8 @@ def sy2sb(A, w: int, b: int | None = None, prec="fp64", lookahead: bool = True,
     if tau is None:
         tau = torch.zeros(max(n - w, 1), dtype=torch.float64, device=A.device)
     p = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
-    o = Opts(1 if lookahead else 0, int(panel_rows), int(panel_method))
+    o = Opts(1 if lookahead else 0, int(panel_rows), int(panel_method), int(update_chunks),
+             int(update_lds_cap))
     h = _stream_handle(stream)
     rc = bandred_sy2sb_ex(n, w, b, A.data_ptr(), lda, tau.data_ptr(), p, o, h)
     _check("bandred_sy2sb_ex", rc)
@@ -268,7 +287,8 @@ def sy2sb(A, w: int, b: int | None = None, prec="fp64", lookahead: bool = True,
 
 
 def ge2gb(A, w: int, b: int | None = None, prec="fp64", lookahead: bool = True,
-          panel_rows: int = 0, panel_method: int = 0, stream=None, check: bool = True):
+          panel_rows: int = 0, panel_method: int = 0, stream=None, check: bool = True,
+          update_chunks: int = 0, update_lds_cap: int = 0):
     """Reduce the column-major CUDA tensor ``A`` (m >= n) to upper
     triangular-band width ``w`` in place; returns (tauq, taup)."""
     import torch
@@ -279,7 +299,8 @@ def ge2gb(A, w: int, b: int | None = None, prec="fp64", lookahead: bool = True,
     tauq = torch.zeros(max(n, 1), dtype=torch.float64, device=A.device)
     taup = torch.zeros(max(n, 1), dtype=torch.float64, device=A.device)
     p = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
-    o = Opts(1 if lookahead else 0, int(panel_rows), int(panel_method))
+    o = Opts(1 if lookahead else 0, int(panel_rows), int(panel_method), int(update_chunks),
+             int(update_lds_cap))
     h = _stream_handle(stream)
     rc = bandred_ge2gb_ex(m, n, w, b, A.data_ptr(), lda, tauq.data_ptr(), taup.data_ptr(), p, o, h)
     _check("bandred_ge2gb_ex", rc)
@@ -288,7 +309,8 @@ def ge2gb(A, w: int, b: int | None = None, prec="fp64", lookahead: bool = True,
 
 
 def ge2gb_lu(A, w: int, b: int | None = None, prec="fp64", lookahead: bool = True,
-             panel_rows: int = 0, panel_method: int = 0, stream=None, check: bool = True):
+             panel_rows: int = 0, panel_method: int = 0, stream=None, check: bool = True,
+             update_chunks: int = 0, update_lds_cap: int = 0):
     """Reduce the column-major CUDA tensor ``A`` (m >= n) to band form with
     lower and upper bandwidth ``w`` in place; returns (tauq, taup)."""
     import torch
@@ -299,7 +321,8 @@ def ge2gb_lu(A, w: int, b: int | None = None, prec="fp64", lookahead: bool = Tru
     tauq = torch.zeros(max(n, 1), dtype=torch.float64, device=A.device)
     taup = torch.zeros(max(n, 1), dtype=torch.float64, device=A.device)
     p = PREC_NAMES[prec] if isinstance(prec, str) else int(prec)
-    o = Opts(1 if lookahead else 0, int(panel_rows), int(panel_method))
+    o = Opts(1 if lookahead else 0, int(panel_rows), int(panel_method), int(update_chunks),
+             int(update_lds_cap))
     h = _stream_handle(stream)
     rc = bandred_ge2gb_lu(m, n, w, b, A.data_ptr(), lda, tauq.data_ptr(), taup.data_ptr(), p, o, h)
     _check("bandred_ge2gb_lu", rc)

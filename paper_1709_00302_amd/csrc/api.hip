@@ -249,6 +249,8 @@ struct Ctx {
   size_t part_cap;  // doubles
   char *oz = nullptr;  // digit planes of the exact-split products (P_OZ)
   size_t oz_cap = 0;   // bytes
+  int max_chunks = 0;  // bandred_opts_t.update_chunks (0: the defaults below)
+  int lds_cap = 0;     // bandred_opts_t.update_lds_cap
 };
 
 // ---------------------------------------------------------------------------
@@ -448,9 +450,15 @@ constexpr int kMaxSyr2kChunks = 2;
 // the cap costs the large updates more than it gains).
 constexpr int kUpdateCapBelow = 8192;
 constexpr int kUpdateCapLds = 20 * 1024;
-static int update_chunks(const DevState *st, int64_t tiles128) {
+static int update_chunks(const DevState *st, int64_t tiles128, int maxc) {
   const int64_t per = 4 * (int64_t)st->num_cu;  // two rounds of two workgroups per CU
-  return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxChunks, tiles128 / per));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(maxc, tiles128 / per));
+}
+// extra LDS of an update launch beside a panel, for an update of `rows` rows
+static int update_lds_pad(const Ctx &cx, int64_t rows) {
+  if (cx.lds_cap == 1) return kUpdateCapLds;
+  if (cx.lds_cap == 2) return 0;
+  return rows <= kUpdateCapBelow ? kUpdateCapLds : 0;
 }
 
 // syr2k over columns [c0, c1) as update_chunks() launches of about equal
@@ -459,7 +467,8 @@ static int syr2k_chunked(Ctx &cx, int prec, int j, int pb, const double *WV, int
                          double *A2, int64_t lda, int c0, int c1, hipStream_t s) {
   if (c1 <= c0) return 0;
   const int64_t nI = (j - c0 + 127) / 128, nJ = (c1 - c0 + 127) / 128;
-  const int nck = std::min(kMaxSyr2kChunks, update_chunks(cx.st, nJ * nI - nJ * (nJ - 1) / 2));
+  const int nck = update_chunks(cx.st, nJ * nI - nJ * (nJ - 1) / 2,
+                                cx.max_chunks > 0 ? cx.max_chunks : kMaxSyr2kChunks);
   auto area = [&](double x) {  // lower-trapezoid elements of columns [c0, x)
     const double r0 = j - c0, r1 = j - x;
     return 0.5 * (r0 * (r0 + 1) - r1 * (r1 + 1));
@@ -473,8 +482,7 @@ static int syr2k_chunked(Ctx &cx, int prec, int j, int pb, const double *WV, int
       hi = lo;
       while (hi < c1 && area(hi) < tot * k / nck) hi = std::min(c1, hi + 128);
     }
-    int rc = syr2k(cx, prec, j, pb, WV, ldwv, A2, lda, lo, hi, s,
-                   j <= kUpdateCapBelow ? kUpdateCapLds : 0);
+    int rc = syr2k(cx, prec, j, pb, WV, ldwv, A2, lda, lo, hi, s, update_lds_pad(cx, j));
     if (rc) return rc;
     lo = hi;
   }
@@ -487,7 +495,8 @@ static int gemm_chunked(Ctx &cx, int cls, int opa, int opb, int prec, int M, int
                         const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
                         int64_t ldc, double alpha, double beta, hipStream_t s, int kseg = 0) {
   const int64_t tiles = (int64_t)((M + 127) / 128) * ((N + 127) / 128);
-  const int nck = (K <= 512) ? update_chunks(cx.st, tiles) : 1;
+  const int nck =
+      (K <= 512) ? update_chunks(cx.st, tiles, cx.max_chunks > 0 ? cx.max_chunks : kMaxChunks) : 1;
   const int nt = (N + 127) / 128;
   for (int k = 0, n0 = 0; k < nck && n0 < N; ++k) {
     const int n1 = (k == nck - 1) ? N : std::min(N, 128 * (int)((int64_t)nt * (k + 1) / nck));
@@ -495,7 +504,7 @@ static int gemm_chunked(Ctx &cx, int cls, int opa, int opb, int prec, int M, int
     const double *Bk = (opb == B_N) ? B + (int64_t)n0 * ldb : B + n0;
     int rc = gemm(cx, cls, opa, opb, prec, M, n1 - n0, K, A, lda, Bk, ldb,
                   C + (int64_t)n0 * ldc, ldc, alpha, beta, s, nullptr, 0, nullptr, 0, 0,
-                  M <= kUpdateCapBelow ? kUpdateCapLds : 0, kseg);
+                  update_lds_pad(cx, M), kseg);
     if (rc) return rc;
     n0 = n1;
   }
@@ -724,6 +733,10 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
   int *pstruct = ar.take<int>((size_t)(npan + 1) * 2 * kNbMax);
 
   Ctx cxm{st, s, partm, part_main};
+  if (opts) {
+    cxm.max_chunks = opts->update_chunks;
+    cxm.lds_cap = opts->update_lds_cap;
+  }
   if (oz_sz) {
     cxm.oz = ar.take<char>(oz_sz);
     cxm.oz_cap = oz_sz;
@@ -899,6 +912,10 @@ static int ge2gb_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, double
   int *pflags = ar.take<int>(2 * (2 * npan + 2));
   int *pstruct = ar.take<int>((size_t)(2 * npan + 2) * 2 * kNbMax);
   Ctx cx{st, s, part, part_cap};
+  if (opts) {
+    cx.max_chunks = opts->update_chunks;
+    cx.lds_cap = opts->update_lds_cap;
+  }
   if (oz_sz) {
     cx.oz = ar.take<char>(oz_sz);
     cx.oz_cap = oz_sz;
@@ -1121,6 +1138,10 @@ static int ge2gb_lu_impl(int64_t m64, int64_t n64, int64_t w64, int64_t b64, dou
   int *pflags = ar.take<int>(2 * (2 * npan + 2));
   int *pstruct = ar.take<int>((size_t)(2 * npan + 2) * 2 * kNbMax);
   Ctx cx{st, s, part, part_cap};
+  if (opts) {
+    cx.max_chunks = opts->update_chunks;
+    cx.lds_cap = opts->update_lds_cap;
+  }
   if (oz_sz) {
     cx.oz = ar.take<char>(oz_sz);
     cx.oz_cap = oz_sz;
@@ -1635,9 +1656,25 @@ static int check_opts(const bandred_opts_t *o) {
   if (o->lookahead != 0 && o->lookahead != 1) return 1;
   if (o->panel_rows < 0) return 1;
   if (o->panel_method < 0 || o->panel_method > 2) return 1;
-  for (int i = 0; i < 5; ++i)
+  if (o->update_chunks < 0 || o->update_chunks > 8) return 1;
+  if (o->update_lds_cap < 0 || o->update_lds_cap > 2) return 1;
+  for (int i = 0; i < 3; ++i)
     if (o->reserved[i] != 0) return 1;
   return 0;
+}
+
+// The options of a call that passed b = 0: the autotuner's knobs where the
+// caller left them at 0.
+static const bandred_opts_t *tuned_opts(const bandred_opts_t *opts, int chunks, int cap,
+                                        bandred_opts_t *buf) {
+  if (opts) *buf = *opts;
+  else {
+    *buf = bandred_opts_t{};
+    buf->lookahead = 1;
+  }
+  if (buf->update_chunks == 0) buf->update_chunks = chunks;
+  if (buf->update_lds_cap == 0) buf->update_lds_cap = cap;
+  return buf;
 }
 
 extern "C" {
@@ -1665,11 +1702,14 @@ int bandred_sy2sb_ex(int64_t n, int64_t w, int64_t b, double *A, int64_t lda, do
   if (rc) return rc;
   if (check_prec(prec)) return -7;
   if (check_opts(opts)) return -8;
-  if (b == 0) {  // the autotuner's block size
+  bandred_opts_t tuned;
+  if (b == 0) {  // the autotuner's block size and update split
     int bt = 0;
-    rc = tune_pick(0, n, n, w, prec, (hipStream_t)stream, &bt);
+    int ch = 0, cap = 0;
+    rc = tune_pick(0, n, n, w, prec, (hipStream_t)stream, &bt, &ch, &cap);
     if (rc) return rc;
     b = bt;
+    opts = tuned_opts(opts, ch, cap, &tuned);
   }
   return sy2sb_impl(n, w, b, A, lda, tau, prec, opts, (hipStream_t)stream);
 }
@@ -1681,11 +1721,14 @@ int bandred_ge2gb_ex(int64_t m, int64_t n, int64_t w, int64_t b, double *A, int6
   if (rc) return rc;
   if (check_prec(prec)) return -9;
   if (check_opts(opts)) return -10;
+  bandred_opts_t tuned;
   if (b == 0) {
     int bt = 0;
-    rc = tune_pick(1, m, n, w, prec, (hipStream_t)stream, &bt);
+    int ch = 0, cap = 0;
+    rc = tune_pick(1, m, n, w, prec, (hipStream_t)stream, &bt, &ch, &cap);
     if (rc) return rc;
     b = bt;
+    opts = tuned_opts(opts, ch, cap, &tuned);
   }
   return ge2gb_impl(m, n, w, b, A, lda, tauq, taup, prec, opts, (hipStream_t)stream);
 }
@@ -1697,11 +1740,14 @@ int bandred_ge2gb_lu(int64_t m, int64_t n, int64_t w, int64_t b, double *A, int6
   if (rc) return rc;
   if (check_prec(prec)) return -9;
   if (check_opts(opts)) return -10;
+  bandred_opts_t tuned;
   if (b == 0) {
     int bt = 0;
-    rc = tune_pick(2, m, n, w, prec, (hipStream_t)stream, &bt);
+    int ch = 0, cap = 0;
+    rc = tune_pick(2, m, n, w, prec, (hipStream_t)stream, &bt, &ch, &cap);
     if (rc) return rc;
     b = bt;
+    opts = tuned_opts(opts, ch, cap, &tuned);
   }
   return ge2gb_lu_impl(m, n, w, b, A, lda, tauq, taup, prec, opts, (hipStream_t)stream);
 }

@@ -126,7 +126,8 @@ int launch_extract_v(const double *A, int64_t lda, int rowstore, int64_t r0, int
                      int j, double *V, int64_t ldv, hipStream_t s);
 // block size picked by the autotuner (tune.hip) for a call with b = 0
 // (kind 0: sy2sb, 1: ge2gb, 2: ge2gb_lu)
-int tune_pick(int kind, int64_t m, int64_t n, int64_t w, int prec, hipStream_t s, int *b_out);
+int tune_pick(int kind, int64_t m, int64_t n, int64_t w, int prec, hipStream_t s, int *b_out,
+              int *chunks, int *cap);
 int tune_lookup(int kind, int64_t m, int64_t n, int64_t w, int prec);
 // stage 2 (stage2.hip): band -> tridiagonal by bulge chasing, tridiagonal eigenvalues
 int launch_sb2st(const double *A, int64_t lda, int n, int w, double *AB, int64_t ldab,

@@ -1,4 +1,5 @@
-// tune.hip -- block-size autotuner of the reductions.
+// tune.hip -- autotuner of the reductions: block size and the split between
+// the look-ahead panel and the update beside it.
 //
 // The paper tunes the algorithmic block size b per problem (n, w) in steps of
 // 16 and shows that the best b depends on both (Sec. 4.2, the role of the
@@ -7,10 +8,15 @@
 // timing: the tuner runs the reduction on a synthetic matrix of the same shape
 // (values from a counter-based hash, so the timing sees no data-dependent
 // fast path) for every candidate b in {16, 32, ..., min(w, 128)} (b = w when
-// w < 16), and keeps the fastest.  Results are cached per device and
-// (kind, m, n, w, prec) in memory and, when the environment variable
-// BANDRED_TUNE_CACHE names a file, in that file (one JSON object per line),
-// which later processes read back.
+// w < 16), and keeps the fastest.  At that b it then times the knobs that
+// share the chip between the panel of the next step and the update beside it
+// (the paper's split of the cores between panel and update, Sec. 2.2): the
+// number of launches the update is issued as (1 .. 4) and whether they leave
+// LDS room on each CU for the panel (on / off); these change no result bit,
+// and a setting is kept when it beats the default rule by more than 1%.
+// Results are cached per device and (kind, m, n, w, prec) in memory and, when
+// the environment variable BANDRED_TUNE_CACHE names a file, in that file (one
+// JSON object per line), which later processes read back.
 //
 // It is built only on the library's public entry points; it allocates the
 // trial matrix and times with HIP events, so it must not run under stream
@@ -56,6 +62,7 @@ struct TuneEntry {
   int dev, kind, prec;
   int64_t m, n, w;
   int b;
+  int chunks, cap;  // bandred_opts_t.update_chunks / update_lds_cap (0: default rule)
 };
 
 std::mutex g_tmu;
@@ -86,42 +93,53 @@ void read_file_locked() {
     for (int k = 0; k < 3; ++k)
       if (strcmp(kname, kind_name(k)) == 0) kind = k;
     if (kind < 0 || b < 1 || b > kNbMax || b > w) continue;
-    g_cache.push_back(TuneEntry{-1, kind, prec, m, n, w, b});  // any device
+    int chunks = 0, cap = 0;
+    if (const char *q = strstr(line, "\"chunks\": ")) chunks = atoi(q + 10);
+    if (const char *q = strstr(line, "\"cap\": ")) cap = atoi(q + 7);
+    if (chunks < 0 || chunks > 8) chunks = 0;
+    if (cap < 0 || cap > 2) cap = 0;
+    g_cache.push_back(TuneEntry{-1, kind, prec, m, n, w, b, chunks, cap});  // any device
   }
   fclose(f);
 }
 
-void append_file(const TuneEntry &e, const std::vector<std::pair<int, float>> &times) {
+void append_file(const TuneEntry &e, const std::vector<std::pair<int, float>> &times,
+                 const std::vector<std::pair<int, float>> &split_times) {
   const char *path = getenv("BANDRED_TUNE_CACHE");
   if (!path || !*path) return;
   FILE *f = fopen(path, "a");
   if (!f) return;
   fprintf(f, "{\"kind\": \"%s\", \"m\": %lld, \"n\": %lld, \"w\": %lld, \"prec\": %d, \"b\": %d, "
-             "\"ms\": {",
-          kind_name(e.kind), (long long)e.m, (long long)e.n, (long long)e.w, e.prec, e.b);
+             "\"chunks\": %d, \"cap\": %d, \"ms\": {",
+          kind_name(e.kind), (long long)e.m, (long long)e.n, (long long)e.w, e.prec, e.b, e.chunks,
+          e.cap);
   for (size_t i = 0; i < times.size(); ++i)
     fprintf(f, "%s\"%d\": %.4f", i ? ", " : "", times[i].first, times[i].second);
+  fprintf(f, "}, \"split_ms\": {");
+  for (size_t i = 0; i < split_times.size(); ++i)  // key: 10 chunks + cap
+    fprintf(f, "%s\"%d\": %.4f", i ? ", " : "", split_times[i].first, split_times[i].second);
   fprintf(f, "}}\n");
   fclose(f);
 }
 
-int lookup_locked(int dev, int kind, int64_t m, int64_t n, int64_t w, int prec) {
+// the cached entry (nullptr when the problem has not been tuned)
+const TuneEntry *lookup_locked(int dev, int kind, int64_t m, int64_t n, int64_t w, int prec) {
   read_file_locked();
-  int found = 0;
+  const TuneEntry *found = nullptr;
   for (const TuneEntry &e : g_cache)
     if ((e.dev == dev || e.dev < 0) && e.kind == kind && e.m == m && e.n == n && e.w == w &&
         e.prec == prec) {
-      found = e.b;
-      if (e.dev == dev) return e.b;  // a measurement on this device wins
+      found = &e;
+      if (e.dev == dev) return found;  // a measurement on this device wins
     }
   return found;
 }
 
 int run_once(int kind, int64_t m, int64_t n, int64_t w, int64_t b, double *A, int64_t lda,
-             double *t1, double *t2, int prec, hipStream_t s) {
-  if (kind == 0) return bandred_sy2sb_ex(n, w, b, A, lda, t1, prec, nullptr, s);
-  if (kind == 1) return bandred_ge2gb_ex(m, n, w, b, A, lda, t1, t2, prec, nullptr, s);
-  return bandred_ge2gb_lu(m, n, w, b, A, lda, t1, t2, prec, nullptr, s);
+             double *t1, double *t2, int prec, const bandred_opts_t *o, hipStream_t s) {
+  if (kind == 0) return bandred_sy2sb_ex(n, w, b, A, lda, t1, prec, o, s);
+  if (kind == 1) return bandred_ge2gb_ex(m, n, w, b, A, lda, t1, t2, prec, o, s);
+  return bandred_ge2gb_lu(m, n, w, b, A, lda, t1, t2, prec, o, s);
 }
 
 }  // namespace
@@ -139,21 +157,21 @@ static std::vector<int> candidates(int64_t w) {
 // Tuned b for the problem (kind 0: sy2sb n x n; 1: ge2gb m x n; 2: ge2gb_lu),
 // measured now unless cached.  times (optional) receives the measured
 // milliseconds per candidate.
-int tune_block(int kind, int64_t m, int64_t n, int64_t w, int prec, int force, int *b_out,
+int tune_block(int kind, int64_t m, int64_t n, int64_t w, int prec, int force, TuneEntry *out,
                std::vector<std::pair<int, float>> *times_out) {
   int dev = 0;
   BR_HIP_CHECK(hipGetDevice(&dev));
   {
     std::lock_guard<std::mutex> lk(g_tmu);
-    const int b = force ? 0 : lookup_locked(dev, kind, m, n, w, prec);
-    if (b > 0) {
-      *b_out = b;
+    const TuneEntry *e = force ? nullptr : lookup_locked(dev, kind, m, n, w, prec);
+    if (e) {
+      *out = *e;
       return 0;
     }
   }
   const std::vector<int> cand = candidates(w);
-  if (cand.size() == 1 || (kind == 0 ? n <= w + 1 : n == 0)) {
-    *b_out = cand.back();
+  if (kind == 0 ? n <= w + 1 : n == 0) {  // nothing to reduce: nothing to time
+    *out = TuneEntry{dev, kind, prec, m, n, w, cand.back(), 0, 0};
     return 0;
   }
   const int64_t rows = (kind == 0) ? n : m;
@@ -187,45 +205,71 @@ int tune_block(int kind, int64_t m, int64_t n, int64_t w, int prec, int force, i
   }
   hipLaunchKernelGGL(k_trial_fill, dim3(1024), dim3(256), 0, s, A0, lda, (int)rows, (int)n,
                      kind == 0 ? 1 : 0, (uint64_t)0x5EEDull);
-  float best = 0.f;
-  int bbest = cand.back();
-  for (int b : cand) {
+  // best of two timed runs after a warm-up, each on a fresh copy of the matrix
+  auto time_setting = [&](int b, const bandred_opts_t *o, float *ms_best) -> int {
     float tmin = 0.f;
-    for (int rep = 0; rep < 3 && rc == 0; ++rep) {  // one warm-up, best of two
-      if (hipMemcpyAsync(A, A0, elems * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) {
-        rc = BANDRED_ERR_HIP;
-        break;
-      }
+    for (int rep = 0; rep < 3; ++rep) {
+      if (hipMemcpyAsync(A, A0, elems * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return BANDRED_ERR_HIP;
       (void)hipEventRecord(ea, s);
-      rc = run_once(kind, m, n, w, b, A, lda, t1, t2, prec, s);
+      const int r = run_once(kind, m, n, w, b, A, lda, t1, t2, prec, o, s);
       (void)hipEventRecord(eb, s);
-      if (rc) break;
-      if (hipEventSynchronize(eb) != hipSuccess) {
-        rc = BANDRED_ERR_HIP;
-        break;
-      }
+      if (r) return r;
+      if (hipEventSynchronize(eb) != hipSuccess) return BANDRED_ERR_HIP;
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, ea, eb);
       if (rep > 0 && (tmin == 0.f || ms < tmin)) tmin = ms;
     }
+    *ms_best = tmin;
+    return 0;
+  };
+  // (1) the block size, with the default split
+  float best = 0.f;
+  int bbest = cand.back();
+  for (int b : cand) {
+    if (cand.size() == 1) break;
+    float t = 0.f;
+    rc = time_setting(b, nullptr, &t);
     if (rc) break;
-    times.emplace_back(b, tmin);
-    if (best == 0.f || tmin < best) {
-      best = tmin;
+    times.emplace_back(b, t);
+    if (best == 0.f || t < best) {
+      best = t;
       bbest = b;
     }
   }
+  // (2) at that b, the update's launches and LDS cap beside the panel
+  int cbest = 0, lbest = 0;
+  std::vector<std::pair<int, float>> split_times;
+  if (rc == 0 && best == 0.f) rc = time_setting(bbest, nullptr, &best);
+  float sbest = best;
+  for (int ch = 1; ch <= 4 && rc == 0; ++ch)
+    for (int cap = 1; cap <= 2 && rc == 0; ++cap) {
+      bandred_opts_t o{};
+      o.lookahead = 1;
+      o.update_chunks = ch;
+      o.update_lds_cap = cap;
+      float t = 0.f;
+      rc = time_setting(bbest, &o, &t);
+      if (rc) break;
+      split_times.emplace_back(10 * ch + cap, t);
+      if (t < sbest) {
+        sbest = t;
+        cbest = ch;
+        lbest = cap;
+      }
+    }
+  if (sbest > 0.99f * best) cbest = lbest = 0;  // within 1% of the default: keep it
   if (rc == 0 && hipStreamSynchronize(s) != hipSuccess) rc = BANDRED_ERR_HIP;
   if (rc == 0) rc = bandred_status(s);
   cleanup();
   if (rc) return rc;
-  TuneEntry e{dev, kind, prec, m, n, w, bbest};
+  TuneEntry e{dev, kind, prec, m, n, w, bbest, cbest, lbest};
   {
     std::lock_guard<std::mutex> lk(g_tmu);
     g_cache.push_back(e);
-    append_file(e, times);
+    append_file(e, times, split_times);
   }
-  *b_out = bbest;
+  *out = e;
   if (times_out) *times_out = times;
   return 0;
 }
@@ -235,7 +279,8 @@ int tune_lookup(int kind, int64_t m, int64_t n, int64_t w, int prec) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   std::lock_guard<std::mutex> lk(g_tmu);
-  return lookup_locked(dev, kind, m, n, w, prec);
+  const TuneEntry *e = lookup_locked(dev, kind, m, n, w, prec);
+  return e ? e->b : 0;
 }
 
 }  // namespace br
@@ -248,14 +293,14 @@ extern "C" int bandred_tune(int kind, int64_t m, int64_t n, int64_t w, int prec,
   if (m < 0) return -2;
   if (n < 0 || (kind != 0 && n > m)) return -3;
   if (w < 1) return -4;
-  if (prec < 0 || prec > 2) return -5;
+  if (prec < 0 || prec > 3) return -5;
   if (b_out == nullptr) return -7;
   if (kind == 0) m = n;
-  int b = 0;
+  TuneEntry e{};
   std::vector<std::pair<int, float>> times;
-  const int rc = tune_block(kind, m, n, w, prec, force, &b, &times);
+  const int rc = tune_block(kind, m, n, w, prec, force, &e, &times);
   if (rc) return rc;
-  *b_out = b;
+  *b_out = e.b;
   if (ms_out)
     for (int i = 0; i < cap; ++i) {
       ms_out[2 * i] = 0.0;
@@ -268,18 +313,43 @@ extern "C" int bandred_tune(int kind, int64_t m, int64_t n, int64_t w, int prec,
   return 0;
 }
 
+extern "C" int bandred_tune_result(int kind, int64_t m, int64_t n, int64_t w, int prec,
+                                   int64_t *b, int *update_chunks, int *update_lds_cap) {
+  if (kind < 0 || kind > 2) return -1;
+  if (kind == 0) m = n;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return BANDRED_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_tmu);
+  const TuneEntry *e = lookup_locked(dev, kind, m, n, w, prec);
+  if (!e) return BANDRED_ERR_UNSUPPORTED;
+  if (b) *b = e->b;
+  if (update_chunks) *update_chunks = e->chunks;
+  if (update_lds_cap) *update_lds_cap = e->cap;
+  return 0;
+}
+
 namespace br {
-// b for a call that passed b = 0: the cached choice, else (outside stream
-// capture) a fresh measurement.
-int tune_pick(int kind, int64_t m, int64_t n, int64_t w, int prec, hipStream_t s, int *b_out) {
-  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-  BR_HIP_CHECK(hipStreamIsCapturing(s, &cap));
-  if (cap != hipStreamCaptureStatusNone) {
-    const int b = tune_lookup(kind, m, n, w, prec);
-    if (b <= 0) return BANDRED_ERR_UNSUPPORTED;  // cannot measure under capture
-    *b_out = b;
-    return 0;
+// b and the update split for a call that passed b = 0: the cached choice,
+// else (outside stream capture) a fresh measurement.
+int tune_pick(int kind, int64_t m, int64_t n, int64_t w, int prec, hipStream_t s, int *b_out,
+              int *chunks, int *cap) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  BR_HIP_CHECK(hipStreamIsCapturing(s, &cs));
+  TuneEntry e{};
+  if (cs != hipStreamCaptureStatusNone) {
+    int dev = 0;
+    BR_HIP_CHECK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_tmu);
+    const TuneEntry *c = lookup_locked(dev, kind, m, n, w, prec);
+    if (!c) return BANDRED_ERR_UNSUPPORTED;  // cannot measure under capture
+    e = *c;
+  } else {
+    const int rc = tune_block(kind, m, n, w, prec, 0, &e, nullptr);
+    if (rc) return rc;
   }
-  return tune_block(kind, m, n, w, prec, 0, b_out, nullptr);
+  *b_out = e.b;
+  *chunks = e.chunks;
+  *cap = e.cap;
+  return 0;
 }
 }  // namespace br

@@ -64,8 +64,12 @@ def test_ex_precision_and_options_checked():
     o = br.Opts(1, 0, 3)
     assert br.bandred_sy2sb_ex(10, 4, 4, FAKE, 10, FAKE, 0, o) == -8
     o = br.Opts(1, 0)
-    o.reserved[3] = 1
+    o.reserved[2] = 1
     assert br.bandred_sy2sb_ex(10, 4, 4, FAKE, 10, FAKE, 0, o) == -8
+    o = br.Opts(1, 0, 0, 9)  # update_chunks above 8
+    assert br.bandred_sy2sb_ex(10, 4, 4, FAKE, 10, FAKE, 0, o) == -8
+    o = br.Opts(1, 0, 0, 0, 3)  # update_lds_cap above 2
+    assert br.bandred_ge2gb_ex(10, 8, 4, 4, FAKE, 10, FAKE, FAKE, 0, o) == -10
     assert br.bandred_ge2gb_ex(10, 8, 4, 4, FAKE, 10, FAKE, FAKE, 9) == -9
 
 

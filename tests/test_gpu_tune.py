@@ -1,8 +1,12 @@
-"""GPU tests of the block-size autotuner (bandred_tune and b = 0 in the _ex
-calls): it measures every candidate b (multiples of 16 up to min(w, 128)),
-picks the fastest, caches the choice in memory and in the JSONL file named by
-BANDRED_TUNE_CACHE, and a reduction called with b = 0 is the reduction with
-the tuned b, bit for bit."""
+"""GPU tests of the autotuner (bandred_tune and b = 0 in the _ex calls): it
+measures every candidate b (multiples of 16 up to min(w, 128)), picks the
+fastest, then at that b the split between the look-ahead panel and the update
+beside it (update_chunks, update_lds_cap); it caches the choice in memory and
+in the JSONL file named by BANDRED_TUNE_CACHE, and a reduction called with
+b = 0 is the reduction with the tuned b, bit for bit.  The split knobs change
+no result bit (every element is computed by one tile in the same k order):
+checked at sizes where the update beside the panel is really cut into
+several launches."""
 import json
 import os
 
@@ -32,6 +36,15 @@ def test_tune_measures_candidates_and_caches(bandred, tmp_path):
         lines = [json.loads(x) for x in open(path).read().splitlines()]
         assert lines[-1]["kind"] == "sy2sb" and lines[-1]["n"] == n and lines[-1]["b"] == b
         assert sorted(int(k) for k in lines[-1]["ms"]) == [16, 32, 48, 64]
+        # the split phase: 4 launch counts x LDS cap on / off, timed at the tuned b
+        assert sorted(int(k) for k in lines[-1]["split_ms"]) == [11, 12, 21, 22, 31, 32, 41, 42]
+        res = bandred.bandred_tune_result(0, n, n, w)
+        assert res == (b, lines[-1]["chunks"], lines[-1]["cap"]), res
+        assert 0 <= res[1] <= 4 and 0 <= res[2] <= 2
+        if res[1]:  # a kept setting beat the default by more than 1%
+            best = min(lines[-1]["split_ms"].values())
+            assert lines[-1]["split_ms"][str(10 * res[1] + res[2])] == best
+        assert bandred.bandred_tune_result(0, 777, 777, 64) is None  # never tuned
         # the other kinds, and w below 16 (b = w, nothing to measure)
         bg, msg = bandred.bandred_tune(1, 1200, 900, 48, force=True)
         assert bg in (16, 32, 48) and len(msg) == 3
@@ -112,3 +125,36 @@ def test_tune_argument_errors(bandred):
     assert lib.bandred_tune(1, 10, 11, 2, 0, 0, ctypes.byref(b), None, 0) == -3
     assert lib.bandred_tune(0, 10, 10, 0, 0, 0, ctypes.byref(b), None, 0) == -4
     assert lib.bandred_tune(0, 10, 10, 2, 0, 0, None, None, 0) == -7
+
+
+@pytest.mark.parametrize("kind,m,n,w", [
+    ("sy2sb", 8192, 8192, 64),
+    ("ge2gb", 8192, 8192, 64),
+    ("ge2gb_lu", 6144, 6144, 64),
+])
+def test_split_knobs_change_no_bit(bandred, kind, m, n, w):
+    """Every update launch count and LDS-cap setting gives the default
+    call's result bit for bit (updates beside the panel are cut into up to 4
+    launches at these sizes)."""
+    print(f"case split knobs {kind} {m}x{n} w={w}", flush=True)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(91)
+    A0 = torch.randn(n, m, dtype=torch.float64, device="cuda", generator=g).T  # column-major
+    if kind == "sy2sb":
+        A0 = (A0 + A0.T).T.contiguous().T  # symmetric, column-major
+    fn = {"sy2sb": bandred.sy2sb, "ge2gb": bandred.ge2gb, "ge2gb_lu": bandred.ge2gb_lu}[kind]
+
+    def run(ch, cap):
+        A = A0.clone(memory_format=torch.preserve_format)
+        out = fn(A, w, w, update_chunks=ch, update_lds_cap=cap)
+        torch.cuda.synchronize()
+        return A, out
+
+    Aref, ref = run(0, 0)
+    for ch, cap in ((1, 2), (4, 1), (2, 2), (3, 1)):
+        A, out = run(ch, cap)
+        if kind == "sy2sb":
+            same = torch.equal(torch.tril(A), torch.tril(Aref)) and torch.equal(out, ref)
+        else:
+            same = torch.equal(A, Aref) and all(torch.equal(x, y) for x, y in zip(out, ref))
+        assert same, (kind, ch, cap)
