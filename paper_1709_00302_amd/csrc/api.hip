@@ -261,7 +261,8 @@ struct Ctx {
 // (each segment padded to a multiple of 64)
 static size_t oz_need(int64_t M, int64_t N, int64_t K) {
   const size_t Kp = round_up((size_t)K, 64) + 64;
-  return 6 * 256 + 24 * (size_t)(M + N) + (size_t)kOzS * (M + N) * Kp;
+  const size_t rows = round_up((size_t)M, 64) + round_up((size_t)N, 64);  // 64-row blocks
+  return 6 * 256 + 24 * (size_t)(M + N) + (size_t)kOzS * rows * Kp;
 }
 // bound over the products of a driver whose dimensions are at most L1, L2
 // (the matrix) and s2 (a block of reflectors), in any roles
@@ -281,6 +282,18 @@ static int gemm_oz(Ctx &cx, int cls, int opa, int opb, int epi, int M, int N, in
                    const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
                    int64_t ldc, double alpha, double beta, int rot, int c0, int c1, double flops,
                    hipStream_t s) {
+  if (epi == E_SYR2K) {
+    // the rows [c0, M) of op(A) and the columns [c0, c1) of op(B) only (the
+    // tiles then start on the 64-row blocks of their planes): C from (c0, c0)
+    if (c1 <= c0 || M <= c0) return 0;
+    A += c0;  // op(A) = A_N: row r at A[r + k lda]
+    B += c0;  // op(B) = B_TROT: column c at B[c + kr ldb]
+    C += c0 + (int64_t)c0 * ldc;
+    M -= c0;
+    N = c1 - c0;
+    c1 = N;
+    c0 = 0;
+  }
   if (!cx.oz || oz_need(M, N, K) > cx.oz_cap) return BANDRED_ERR_UNSUPPORTED;
   int L0 = 0;
   const int Kp = oz_plane_cols(K, ks, &L0);
@@ -288,8 +301,8 @@ static int gemm_oz(Ctx &cx, int cls, int opa, int opb, int epi, int M, int N, in
   unsigned long long *mxa = ar.take<unsigned long long>(2 * (size_t)M);
   unsigned long long *mxb = ar.take<unsigned long long>(2 * (size_t)N);
   int *ea = ar.take<int>(2 * (size_t)M), *eb = ar.take<int>(2 * (size_t)N);
-  int8_t *PA = ar.take<int8_t>((size_t)kOzS * M * Kp);
-  int8_t *PB = ar.take<int8_t>((size_t)kOzS * N * Kp);
+  int8_t *PA = ar.take<int8_t>((size_t)kOzS * round_up((size_t)M, 64) * Kp);
+  int8_t *PB = ar.take<int8_t>((size_t)kOzS * round_up((size_t)N, 64) * Kp);
   const int *abort = cx.st->flags + 1;
   ProfScope ps(cls, flops, s);
   int rc = oz_slice(A, lda, opa, M, K, ks, 0, 0, mxa, ea, PA, s);
@@ -299,12 +312,13 @@ static int gemm_oz(Ctx &cx, int cls, int opa, int opb, int epi, int M, int N, in
   if (epi == E_SYR2K)
     return oz_gemm(E_SYR2K, PA, PB, ea, eb, M, N, Kp, L0, 1, Kp, C, ldc, 1.0, 0.0, nullptr, c0,
                    c1, abort, s);
-  // one 64 x 64 workgroup per CU is resident: split k when the tiles do not
-  // fill the chip (chunks of at least 256, partial sums within the buffer)
+  // two 64 x 64 workgroups per CU are resident: split k when the tiles do
+  // not fill the chip (chunks of at least 256, partial sums within the buffer)
   const int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
+  const int64_t slots = 2 * (int64_t)cx.st->num_cu;
   int nk = 1;
-  if (tiles < cx.st->num_cu && Kp >= 512) {
-    nk = (int)std::min<int64_t>((2 * cx.st->num_cu + tiles - 1) / tiles, Kp / 256);
+  if (tiles < slots && Kp >= 512) {
+    nk = (int)std::min<int64_t>((2 * slots + tiles - 1) / tiles, Kp / 256);
     while (nk > 1 && (size_t)nk * M * N > cx.part_cap) --nk;
   }
   if (nk <= 1)

@@ -27,10 +27,10 @@
 // C_ij is below 2^-49 sum_s K_s max_k|a_ik| max_k|b_kj|, under the worst-case
 // bound of an FP64 dot product of length K.
 //
-// Slices are stored as planes: plane p of op(A) is M x Kp int8 with k
-// contiguous (each segment zero padded to a multiple of 64, Kp the sum),
-// plane q of op(B) N x Kp likewise.  The product kernel stages 64 x 64 blocks
-// of every plane through LDS (double buffered); a lane's 16 bytes of an MFMA
+// Slices are stored as planes: plane p of op(A) holds M rows of Kp int8
+// (each segment zero padded to a multiple of 64, Kp the sum), plane q of
+// op(B) N rows likewise, in 64 x 64 blocks (below).  The product kernel
+// copies the blocks of every plane into LDS; a lane's 16 bytes of an MFMA
 // operand are one LDS read.
 // v_mfma_i32_16x16x64_i8 (measured on gfx950): lane l supplies A(l % 16,
 // 16 (l / 16) + e) and B(16 (l / 16) + e, l % 16) as bytes e = 0..15 and
@@ -40,6 +40,16 @@
 namespace br {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+
+// The planes are stored in 64 x 64 blocks: block (rb, kb) of plane p (rows
+// 64 rb .., plane columns 64 kb ..) is the 4 KB at ((rb nKB + kb) kOzS + p)
+// kOzBlk, nKB = Kp / 64, holding row r's 16-byte chunk c at oz_swz(r, c):
+// 64 r + 16 (c ^ ((r / 4) mod 4)).  That is also the block's image in the
+// product kernel's LDS (a straight copy), where the 16 rows one MFMA operand
+// read touches fall on distinct banks.  Rows are padded to a multiple of 64.
+__device__ __forceinline__ int oz_swz(int r, int c) { return r * 64 + ((c ^ ((r >> 2) & 3)) << 4); }
+constexpr int kOzBlk = 64 * 64;             // bytes of one plane's block
+constexpr int kOzStage = 2 * kOzS * kOzBlk; // both operands, all planes
 
 // Operand x of a product as rows: row r, entry k is op(A)(r, k) (isB = 0) or
 // op(B)(k, r) (isB = 1).  The symmetric pattern reads the lower triangle
@@ -150,7 +160,7 @@ __global__ void k_oz_exps(const unsigned long long *rmax, int count, int *ex) {
 // digit of weight 256^k (that subtraction makes the carries: Y = Z - C), and
 // as an int8 it is the byte with its top bit flipped.  Y is assembled from
 // two exact 32-bit conversions.
-__device__ __forceinline__ void oz_digits4(const double *v, int e, int8_t *dst, int64_t plane) {
+__device__ __forceinline__ void oz_digits4(const double *v, int e, unsigned *w) {
   unsigned zl[4], zh[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -165,19 +175,21 @@ __device__ __forceinline__ void oz_digits4(const double *v, int e, int8_t *dst, 
 #pragma unroll
   for (int p = 0; p < kOzS; ++p) {  // plane p holds the digit of weight 256^(6 - p)
     const int k = kOzS - 1 - p;
-    unsigned w = 0;
+    unsigned x = 0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const unsigned src = k < 4 ? zl[c] : zh[c];
-      w |= ((src >> (8 * (k & 3))) & 0xffu) << (8 * c);
+      x |= ((src >> (8 * (k & 3))) & 0xffu) << (8 * c);
     }
-    *(unsigned *)(dst + p * plane) = w ^ 0x80808080u;
+    w[p] = x ^ 0x80808080u;
   }
 }
 
-// planes[p][r][c] = digit p + 1 of the entry of row r at plane column c
-// (zero in the padding).  A symmetric operand stages its lower blocks only
-// and writes each one twice (as rows and, mirrored, as columns).
+// The digit planes of the operand (blocked as above; zero in the padding).
+// Thread t writes bytes 16 t .. 16 t + 15 of every plane's block: row t / 4,
+// chunk (t % 4) ^ ((t / 16) % 4), 16 entries.  A symmetric operand stages
+// its lower blocks only and writes each one twice (as rows and, mirrored, as
+// columns).
 __global__ __launch_bounds__(256) void k_oz_slice(OzSrc s, const int *ex, int8_t *planes) {
   const int kb = blockIdx.x, rb = blockIdx.y;
   const bool sym = !s.isB && s.op == A_SYM;
@@ -187,28 +199,34 @@ __global__ __launch_bounds__(256) void k_oz_slice(OzSrc s, const int *ex, int8_t
   __shared__ double t[64][65];
   oz_stage(s, rb * 64, k0, klim, t);
   __syncthreads();
-  const int64_t plane = (int64_t)s.rows * s.Kp;
+  const int nKB = s.Kp / 64;
   const int *exs = ex + (int64_t)seg * s.rows;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, rl = tid >> 2, c = (tid & 3) ^ ((rl >> 2) & 3);
   const int passes = (sym && rb > kb) ? 2 : 1;
   for (int pass = 0; pass < passes; ++pass) {
-    const int R0 = pass ? kb * 64 : rb * 64, C0 = pass ? rb * 64 : kb * 64;
+    const int RB = pass ? kb : rb, KB = pass ? rb : kb;
+    const int r = RB * 64 + rl;
+    const int e = r < s.rows ? exs[r] : 0;
+    unsigned w[4][kOzS];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int task = tid + 256 * i;  // 64 rows x 16 groups of 4 entries
-      const int rl = task >> 4, g = task & 15;
-      const int r = R0 + rl;
-      if (r >= s.rows) continue;
+    for (int g = 0; g < 4; ++g) {
       double v[4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) v[c] = pass ? t[4 * g + c][rl] : t[rl][4 * g + c];
-      oz_digits4(v, exs[r], planes + (int64_t)r * s.Kp + C0 + 4 * g, plane);
+      for (int x = 0; x < 4; ++x) {
+        const int kl = 16 * c + 4 * g + x;
+        v[x] = pass ? t[kl][rl] : t[rl][kl];
+      }
+      oz_digits4(v, e, w[g]);
     }
+    int8_t *dst = planes + ((int64_t)RB * nKB + KB) * kOzS * kOzBlk + 16 * tid;
+#pragma unroll
+    for (int p = 0; p < kOzS; ++p)
+      *(v4i *)(dst + p * kOzBlk) = v4i{(int)w[0][p], (int)w[1][p], (int)w[2][p], (int)w[3][p]};
   }
 }
 
 struct OzDesc {
-  const int8_t *PA, *PB;   // planes of op(A) (M x Kp each) and op(B) (N x Kp each)
+  const int8_t *PA, *PB;   // blocked planes of op(A) (M rows) and op(B) (N rows)
   const int *ea, *eb;      // exponents: ea[seg M + row], eb[seg N + col]
   int M, N, Kp, L0;        // plane columns, and where segment 1 starts
   int kchunk;              // k range of one blockIdx.z (multiple of 64)
@@ -221,17 +239,16 @@ struct OzDesc {
   const int *abort;
 };
 
-// LDS image of one plane's 64 x 64 block: row r, 16-byte chunk c at
-// 64 r + 16 (c ^ ((r / 4) mod 4)), so that the 16 rows one MFMA operand read
-// touches fall on distinct banks
-__device__ __forceinline__ int oz_swz(int r, int c) { return r * 64 + ((c ^ ((r >> 2) & 3)) << 4); }
-constexpr int kOzBlk = 64 * 64;             // bytes of one plane's block
-constexpr int kOzStage = 2 * kOzS * kOzBlk; // both operands, all planes
 
-// 64 x 64 output tile, 4 waves as 2 x 2 (32 x 32 each: 2 x 2 blocks of 16 x 16)
+// 64 x 64 output tile, 4 waves as 2 x 2 (32 x 32 each: 2 x 2 blocks of 16 x 16).
+// One LDS stage buffer (56 KB) and at most 256 registers per lane, so that
+// two workgroups share a CU and hide each other's stage loads, per-tile
+// prologue and C round trip (measured on SY2SB n=16384 against a
+// double-buffered ring with one workgroup per CU: SYR2K products 99.6 ->
+// 81.6 ms, SYMM products about 59 -> 52 ms).
 template <int EPI>
-__global__ __launch_bounds__(256) void k_gemm_oz(OzDesc d) {
-  __shared__ __attribute__((aligned(16))) int8_t lds[2 * kOzStage];
+__global__ __launch_bounds__(256, 2) void k_gemm_oz(OzDesc d) {
+  __shared__ __attribute__((aligned(16))) int8_t lds[kOzStage];
   if (d.abort && *d.abort != 0) return;
   // one tile per workgroup: the SYR2K enumerates only the tiles that reach
   // the lower triangle (column J holds row blocks J .. nI-1), the others
@@ -262,27 +279,24 @@ __global__ __launch_bounds__(256) void k_gemm_oz(OzDesc d) {
   const int Nlim = (EPI == E_SYR2K) ? d.c1 : d.N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  const int64_t planeA = (int64_t)d.M * d.Kp, planeB = (int64_t)d.N * d.Kp;
-  // staging, global -> LDS without registers: wave w moves rows 16 w ..
-  // 16 w + 15 of every plane's block of both operands, 1 KB per instruction
-  // written lane-contiguously; lane L lands at 16 L = 64 (L / 4) + 16 (L % 4)
-  // of the rows' image, which under the swizzle holds chunk
-  // (L % 4) ^ ((row / 4) % 4) of row 16 w + L / 4.  Rows beyond the matrix
-  // read row 0; their results are dropped.
+  // staging, global -> LDS without registers: the blocks are stored as their
+  // LDS image, so wave w copies bytes 1024 w .. 1024 w + 1023 of every
+  // plane's block of both operands, one 16-byte piece per lane (written
+  // lane-contiguously by the instruction)
   const int wv = __builtin_amdgcn_readfirstlane(wave);
-  const int sr = 16 * wv + (lane >> 2);
-  const int sc = (lane & 3) ^ ((sr >> 2) & 3);
   typedef __attribute__((address_space(1))) const void gvoid;
   typedef __attribute__((address_space(3))) void lvoid;
-  const int8_t *gA = d.PA + (int64_t)(i0 + sr < d.M ? i0 + sr : 0) * d.Kp + 16 * sc;
-  const int8_t *gB = d.PB + (int64_t)(j0 + sr < d.N ? j0 + sr : 0) * d.Kp + 16 * sc;
-  auto issue_stage = [&](int k0, int buf) {
-    int8_t *base = lds + buf * kOzStage + wv * 1024;
+  const int64_t rowblk = (int64_t)(d.Kp / 64) * kOzS * kOzBlk;  // one 64-row block, all planes
+  const int8_t *gA = d.PA + (int64_t)(i0 / 64) * rowblk + wv * 1024 + 16 * lane;
+  const int8_t *gB = d.PB + (int64_t)(j0 / 64) * rowblk + wv * 1024 + 16 * lane;
+  auto issue_stage = [&](int k0) {
+    int8_t *base = lds + wv * 1024;
+    const int64_t kofs = (int64_t)(k0 / 64) * kOzS * kOzBlk;
 #pragma unroll
     for (int p = 0; p < kOzS; ++p) {
-      __builtin_amdgcn_global_load_lds((gvoid *)(gA + p * planeA + k0), (lvoid *)(base + p * kOzBlk),
+      __builtin_amdgcn_global_load_lds((gvoid *)(gA + kofs + p * kOzBlk), (lvoid *)(base + p * kOzBlk),
                                        16, 0, 0);
-      __builtin_amdgcn_global_load_lds((gvoid *)(gB + p * planeB + k0),
+      __builtin_amdgcn_global_load_lds((gvoid *)(gB + kofs + p * kOzBlk),
                                        (lvoid *)(base + (kOzS + p) * kOzBlk), 16, 0, 0);
     }
   };
@@ -329,7 +343,7 @@ __global__ __launch_bounds__(256) void k_gemm_oz(OzDesc d) {
   };
   const int nst = (kend - kbeg) / 64;
   if (nst > 0) {
-    issue_stage(kbeg, 0);
+    issue_stage(kbeg);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
   }
@@ -342,10 +356,14 @@ __global__ __launch_bounds__(256) void k_gemm_oz(OzDesc d) {
     int stop = min(nst, st + kOzKF / 64);
     if (seg == 0) stop = min(stop, (d.L0 - kbeg) / 64);
     for (; st < stop; ++st) {
-      const int8_t *A = lds + (st & 1) * kOzStage, *B = A + kOzS * kOzBlk;
-      // the next stage into the other buffer (last read before the previous
-      // barrier), in flight during this stage's products
-      if (st + 1 < nst) issue_stage(kbeg + 64 * (st + 1), (st + 1) & 1);
+      const int8_t *A = lds, *B = A + kOzS * kOzBlk;
+      if (st > 0) {
+        // this stage into the buffer (its readers passed the barrier that
+        // ended the previous stage)
+        issue_stage(kbeg + 64 * st);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+      }
       v4i bq[kOzS][2];
 #pragma unroll
       for (int q = 0; q < kOzS; ++q)
