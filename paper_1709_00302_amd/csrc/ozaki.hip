@@ -90,16 +90,24 @@ __device__ __forceinline__ void oz_block(const OzSrc &s, int kb, int *seg, int *
 
 // Stage the 64 x 64 block (rows r0.., entries k0.. below klim) into t[r][k]
 // with loads that follow the contiguous dimension; other entries are 0.
+// All 16 loads of a thread are issued before its first LDS store.
 __device__ __forceinline__ void oz_stage(const OzSrc &s, int r0, int k0, int klim,
                                          double (*t)[65]) {
   const int tid = threadIdx.x;
   const bool rc = oz_row_contig(s);
-#pragma unroll 4
+  double v[16];
+#pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int a = tid & 63, c = (tid >> 6) + 4 * i;
     const int rl = rc ? a : c, kl = rc ? c : a;
     const int r = r0 + rl, k = k0 + kl;
-    t[rl][kl] = (r < s.rows && k < klim) ? oz_at(s, r, k) : 0.0;
+    v[i] = (r < s.rows && k < klim) ? oz_at(s, r, k) : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int a = tid & 63, c = (tid >> 6) + 4 * i;
+    const int rl = rc ? a : c, kl = rc ? c : a;
+    t[rl][kl] = v[i];
   }
 }
 
