@@ -251,6 +251,12 @@ struct Ctx {
   size_t oz_cap = 0;   // bytes
   int max_chunks = 0;  // bandred_opts_t.update_chunks (0: the defaults below)
   int lds_cap = 0;     // bandred_opts_t.update_lds_cap
+  // exact split, SY2SB: the SYR2K records the row maxima of the next
+  // trailing matrix (indices >= oz_rec_off of the current one) into oz_rec,
+  // and the next SYMM slices its symmetric operand with them (oz_rmax_in)
+  unsigned long long *oz_rec = nullptr;
+  int oz_rec_off = 0;
+  const unsigned long long *oz_rmax_in = nullptr;
 };
 
 // ---------------------------------------------------------------------------
@@ -282,6 +288,7 @@ static int gemm_oz(Ctx &cx, int cls, int opa, int opb, int epi, int M, int N, in
                    const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
                    int64_t ldc, double alpha, double beta, int rot, int c0, int c1, double flops,
                    hipStream_t s) {
+  const int rec_off = cx.oz_rec_off - c0;  // (in the coordinates from (c0, c0))
   if (epi == E_SYR2K) {
     // the rows [c0, M) of op(A) and the columns [c0, c1) of op(B) only (the
     // tiles then start on the 64-row blocks of their planes): C from (c0, c0)
@@ -305,13 +312,14 @@ static int gemm_oz(Ctx &cx, int cls, int opa, int opb, int epi, int M, int N, in
   int8_t *PB = ar.take<int8_t>((size_t)kOzS * round_up((size_t)N, 64) * Kp);
   const int *abort = cx.st->flags + 1;
   ProfScope ps(cls, flops, s);
-  int rc = oz_slice(A, lda, opa, M, K, ks, 0, 0, mxa, ea, PA, s);
+  int rc = oz_slice(A, lda, opa, M, K, ks, 0, 0, mxa, ea, PA, s,
+                    opa == A_SYM ? cx.oz_rmax_in : nullptr);
   if (rc) return rc;
   rc = oz_slice(B, ldb, opb, N, K, ks, rot, 1, mxb, eb, PB, s);
   if (rc) return rc;
   if (epi == E_SYR2K)
     return oz_gemm(E_SYR2K, PA, PB, ea, eb, M, N, Kp, L0, 1, Kp, C, ldc, 1.0, 0.0, nullptr, c0,
-                   c1, abort, s);
+                   c1, abort, s, cx.oz_rec, rec_off);
   // two 64 x 64 workgroups per CU are resident: split k when the tiles do
   // not fill the chip (chunks of at least 256, partial sums within the buffer)
   const int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
@@ -717,6 +725,7 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
   need += round_up((size_t)(npan + 1) * 2 * kNbMax * 4, 256);  // panel structure
   const size_t oz_sz = prec == P_OZ ? oz_bound(jmax, jmax, 2 * std::max(b, w)) : 0;
   need += oz_sz;
+  if (prec == P_OZ) need += round_up((size_t)jmax * 8, 256);  // row maxima of A2
   need += 8192;
   std::lock_guard<std::mutex> lk(g_mu);
   bool capturing = false;
@@ -751,9 +760,12 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
     cxm.max_chunks = opts->update_chunks;
     cxm.lds_cap = opts->update_lds_cap;
   }
+  unsigned long long *oz_rm = nullptr;  // row maxima of the trailing matrix (exact split)
+  bool rm_valid = false;                // oz_rm holds those of this iteration's A2
   if (oz_sz) {
     cxm.oz = ar.take<char>(oz_sz);
     cxm.oz_cap = oz_sz;
+    oz_rm = ar.take<unsigned long long>(jmax);
   }
   hipStream_t ps = lookahead ? st->aux : s;  // panel stream
   Ctx cxp{st, ps, partp, part_pan};
@@ -845,7 +857,9 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
     rc = update_a1(a1L, a1w);  // A1^R (empty in Variant V2)
     if (rc) return rc;
     // (4) X = A2 Wt (SYMM) into W's slot; M = Wt^T X; W = X - 1/2 V M
+    if (rm_valid) cxm.oz_rmax_in = oz_rm;
     rc = gemm(cxm, C_SYMM, A_SYM, B_N, prec, j, pb, j, A2, lda, Wt, j, W, j, 1.0, 0.0, s);
+    cxm.oz_rmax_in = nullptr;
     if (rc) return rc;
     rc = gemm(cxm, C_GEMM_SMALL, A_T, B_N, P_F64, pb, pb, j, Wt, j, W, j, Mb, pb, 1.0, 0.0, s);
     if (rc) return rc;
@@ -859,11 +873,24 @@ static int sy2sb_impl(int64_t n64, int64_t w64, int64_t b64, double *A, int64_t 
       if (rc) return rc;
       if (head_recorded) BR_HIP_CHECK(hipStreamWaitEvent(s, st->ev_h, 0));
     }
-    // the rest beside the next panel: in chunks (see update_chunks)
+    // the rest beside the next panel: in chunks (see update_chunks).  In the
+    // exact split it writes every stored entry of the next trailing matrix
+    // (columns >= b, the next panel's columns lying below b) and records its
+    // row maxima for the next SYMM.
+    rm_valid = false;
+    if (prec == P_OZ && has_next) {
+      rc = launch_fill_u32((unsigned *)oz_rm, 2 * (int64_t)(j - b), 0u, s);
+      if (rc) return rc;
+      cxm.oz_rec = oz_rm;
+      cxm.oz_rec_off = b;
+      rm_valid = true;
+    }
     if (has_next && ps != s)
       rc = syr2k_chunked(cxm, prec, j, pb, WV, j, A2, lda, a2L, j, s);
     else
       rc = syr2k(cxm, prec, j, pb, WV, j, A2, lda, a2L, j, s);
+    cxm.oz_rec = nullptr;
+    cxm.oz_rec_off = 0;
     if (rc) return rc;
     if (has_next && ps != s) {
       BR_HIP_CHECK(hipEventRecord(st->ev_b, ps));

@@ -143,11 +143,17 @@ int oz_plane_cols(int K, int ks, int *L0);
 // op(A) (isB = 0) or op(B) (isB = 1) as rows of kOzS int8 digit planes
 // (rows x Kp each) with exponents ex[seg rows + r]; rmax is scratch of
 // 2 rows words of 64 bits
+// (rmax_in: the row maxima already known, as the bits of the doubles -- one
+// segment; the pass that finds them is skipped)
 int oz_slice(const double *X, int64_t ld, int op, int rows, int K, int ks, int rot, int isB,
-             unsigned long long *rmax, int *ex, int8_t *planes, hipStream_t s);
+             unsigned long long *rmax, int *ex, int8_t *planes, hipStream_t s,
+             const unsigned long long *rmax_in = nullptr);
+// (rec, SYR2K only: atomicMax of the result's row and column maxima for
+// indices >= rec_off into rec[index - rec_off])
 int oz_gemm(int epi, const int8_t *PA, const int8_t *PB, const int *ea, const int *eb, int M,
             int N, int Kp, int L0, int ksplit, int kchunk, double *C, int64_t ldc, double alpha,
-            double beta, double *part, int c0, int c1, const int *abort, hipStream_t s);
+            double beta, double *part, int c0, int c1, const int *abort, hipStream_t s,
+            unsigned long long *rec = nullptr, int rec_off = 0);
 constexpr int kPackedMax = kNbMax * (kNbMax + 1) / 2;
 int launch_fill(double *p, int64_t count, double v, hipStream_t s);
 int launch_fill_u32(unsigned *p, int64_t count, unsigned v, hipStream_t s);

@@ -243,6 +243,8 @@ struct OzDesc {
   double alpha, beta;
   double *part;            // split-k partials (E_PART)
   int c0, c1;              // SYR2K column range
+  unsigned long long *rec; // SYR2K: row / column maxima of the result (or null) ...
+  int rec_off;             // ... for indices >= rec_off, stored at index - rec_off
   int nI, nJ, nZ;          // tiles: row blocks, column blocks, k chunks
   const int *abort;
 };
@@ -396,7 +398,18 @@ __global__ __launch_bounds__(256, 2) void k_gemm_oz(OzDesc d) {
     }
     fold(seg);
   }
-  // element e of block (a, b) is row 4 (lane / 16) + e, column lane % 16
+  // element e of block (a, b) is row 4 (lane / 16) + e, column lane % 16.
+  // SYR2K with d.rec: the largest |new value| of every row and every column
+  // with index >= d.rec_off (a trailing block of the symmetric matrix, whose
+  // row maxima are those of its stored rows and columns) goes to
+  // d.rec[index - rec_off], one atomicMax per row / column and wave.
+  double rowm[2][4], colm[2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    colm[a] = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rowm[a][e] = 0.0;
+  }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -416,9 +429,46 @@ __global__ __launch_bounds__(256, 2) void k_gemm_oz(OzDesc d) {
           d.part[(int64_t)z * d.M * d.N + row + (int64_t)col * d.M] = v;
         } else {
           double *c = d.C + row + (int64_t)col * d.ldc;
-          *c = *c - v;
+          const double x = *c - v;
+          *c = x;
+          if (col >= d.rec_off) {
+            rowm[a][e] = fmax(rowm[a][e], fabs(x));
+            colm[b] = fmax(colm[b], fabs(x));
+          }
         }
       }
+  if (EPI == E_SYR2K && d.rec) {
+    // the tile's row and column maxima: over the lanes of a wave by
+    // shuffles, over the two waves sharing a row (column) block in LDS, then
+    // one atomicMax per row and column of the tile
+    __syncthreads();  // every wave is done with the stage buffer
+    double *rmx = (double *)lds, *cmx = rmx + 2 * 64;  // [2 waves][64]
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {  // the 16 lanes of one row: lane % 16 varies
+        double m = rowm[a][e];
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) m = fmax(m, __shfl_xor(m, off));
+        if ((lane & 15) == 0) rmx[wn * 64 + wm * 32 + a * 16 + 4 * (lane >> 4) + e] = m;
+      }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {  // the 4 lanes of one column: lane / 16 varies
+      double m = colm[b];
+      m = fmax(m, __shfl_xor(m, 16));
+      m = fmax(m, __shfl_xor(m, 32));
+      if ((lane >> 4) == 0) cmx[wm * 64 + wn * 32 + b * 16 + (lane & 15)] = m;
+    }
+    __syncthreads();
+    const int tid = threadIdx.x;
+    if (tid < 128) {
+      const int x = tid & 63;
+      const double m = (tid < 64) ? fmax(rmx[x], rmx[64 + x]) : fmax(cmx[x], cmx[64 + x]);
+      const int idx = ((tid < 64) ? i0 : j0) + x;
+      if (m > 0.0 && idx >= d.rec_off)
+        atomicMax(d.rec + (idx - d.rec_off), (unsigned long long)__double_as_longlong(m));
+    }
+  }
 }
 
 int oz_plane_cols(int K, int ks, int *L0) {
@@ -428,7 +478,8 @@ int oz_plane_cols(int K, int ks, int *L0) {
 }
 
 int oz_slice(const double *X, int64_t ld, int op, int rows, int K, int ks, int rot, int isB,
-             unsigned long long *rmax, int *ex, int8_t *planes, hipStream_t s) {
+             unsigned long long *rmax, int *ex, int8_t *planes, hipStream_t s,
+             const unsigned long long *rmax_in) {
   if (rows <= 0) return 0;
   if (ks <= 0 || ks >= K) ks = K;
   int L0 = 0;
@@ -436,11 +487,16 @@ int oz_slice(const double *X, int64_t ld, int op, int rows, int K, int ks, int r
   if (op == A_SYM && !isB && ks != K) return BANDRED_ERR_UNSUPPORTED;
   OzSrc src{X, ld, op, isB, rows, K, rot, ks, L0, Kp};
   const int nseg = (ks < K) ? 2 : 1;
-  int rc = launch_fill_u32((unsigned *)rmax, 2 * (int64_t)nseg * rows, 0u, s);
-  if (rc) return rc;
+  if (rmax_in && nseg != 1) return BANDRED_ERR_UNSUPPORTED;
   const dim3 grid(Kp / 64, (rows + 63) / 64);
-  hipLaunchKernelGGL(k_oz_rowmax, grid, dim3(256), 0, s, src, rmax);
-  BR_HIP_CHECK(hipGetLastError());
+  if (rmax_in) {
+    rmax = const_cast<unsigned long long *>(rmax_in);  // (read only below)
+  } else {
+    int rc = launch_fill_u32((unsigned *)rmax, 2 * (int64_t)nseg * rows, 0u, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_oz_rowmax, grid, dim3(256), 0, s, src, rmax);
+    BR_HIP_CHECK(hipGetLastError());
+  }
   hipLaunchKernelGGL(k_oz_exps, dim3((nseg * rows + 255) / 256), dim3(256), 0, s,
                      (const unsigned long long *)rmax, nseg * rows, ex);
   BR_HIP_CHECK(hipGetLastError());
@@ -451,8 +507,11 @@ int oz_slice(const double *X, int64_t ld, int op, int rows, int K, int ks, int r
 
 int oz_gemm(int epi, const int8_t *PA, const int8_t *PB, const int *ea, const int *eb, int M,
             int N, int Kp, int L0, int ksplit, int kchunk, double *C, int64_t ldc, double alpha,
-            double beta, double *part, int c0, int c1, const int *abort, hipStream_t s) {
+            double beta, double *part, int c0, int c1, const int *abort, hipStream_t s,
+            unsigned long long *rec, int rec_off) {
   OzDesc d{};
+  d.rec = rec;
+  d.rec_off = rec_off;
   d.PA = PA; d.PB = PB; d.ea = ea; d.eb = eb;
   d.M = M; d.N = N; d.Kp = Kp; d.L0 = L0; d.kchunk = kchunk;
   d.C = C; d.ldc = ldc; d.alpha = alpha; d.beta = beta; d.part = part;
