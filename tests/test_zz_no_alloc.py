@@ -67,6 +67,30 @@ def test_noalloc_matches_ex_twice_second_smaller(bandred, orc, prec):
         assert torch.isnan(An[n:]).all()
 
 
+def test_noalloc_int8split_matches_ex(bandred):
+    """The exact int8 split through the fixed array (its digit planes and the
+    row maxima the SYR2K records live there too): the same bits as the
+    allocating call, twice, the second call smaller; a problem whose planes
+    do not fit is refused."""
+    for n, w, b, seed in [(1000, 64, 64, 91), (600, 48, 32, 92)]:
+        print(f"case noalloc int8split n={n} w={w} b={b}", flush=True)
+        A = inputs.sym_normal(n, seed)
+        A0, lda = to_device_colmajor(A, n)
+        An = A0.clone()
+        tn = _run_noalloc(bandred, An, lda, n, w, b, 3)
+        for la in (0, 1):
+            Ae = A0.clone()
+            te = _run_ex(bandred, Ae, lda, n, w, b, la, 3)
+            assert torch.equal(torch.tril(An), torch.tril(Ae)), (n, la)
+            assert torch.equal(tn, te), (n, la)
+    n, w = 2050, 128
+    A0, lda = to_device_colmajor(inputs.sym_normal(n, 93), n)
+    tau = torch.zeros(n - w, dtype=torch.float64, device="cuda")
+    s = torch.cuda.current_stream()
+    rc = bandred.bandred_sy2sb_noalloc(n, w, w, A0.data_ptr(), lda, tau.data_ptr(), 3,
+                                       s.cuda_stream)
+    assert rc == UNSUPPORTED  # fits in FP64 (see above), not with the digit planes
+
 def test_noalloc_rejects_what_does_not_fit(bandred):
     n, w = 4000, 128  # needs about 69 MiB of the 64 MiB array
     A = torch.zeros((n, n), dtype=torch.float64, device="cuda")
