@@ -344,31 +344,6 @@ def bench_batched(args, br, inputs, metrics):
         forms["per_matrix_launches"] = {"gflops": flops / (m3 / 1e3) / 1e9, "ms_per_step": m3,
                                         "batched_speedup": m3 / ms}
 
-    pipeline = None
-    if kind == "sy" and not args.no_pipeline:
-        # the two-stage eigenvalue pipeline the paper times after its first
-        # stage (Sec. 4.3): band -> tridiagonal, then the eigenvalues, on the
-        # band of the last timed result
-        log("bench: stage 2 and eigenvalues")
-        t2, t3 = [], []
-        for _ in range(2):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e2 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            dg, eg = br.sb2st(A, w, check=False)
-            e1.record(stream)
-            lam = br.tridiag_eigvals(dg, eg)
-            e2.record(stream)
-            torch.cuda.synchronize()
-            t2.append(e0.elapsed_time(e1))
-            t3.append(e1.elapsed_time(e2))
-        pipeline = {"stage1_ms": ms, "sb2st_ms": min(t2), "tridiag_eig_ms": min(t3),
-                    "total_ms": ms + min(t2) + min(t3)}
-        if "lam" in p:
-            ref = torch.sort(torch.as_tensor(p["lam"], dtype=torch.float64)).values
-            pipeline["eig_err_vs_known"] = float((lam.cpu() - ref).abs().max() / ref.abs().max())
-
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle, bounded sample)")
@@ -402,7 +377,6 @@ def bench_batched(args, br, inputs, metrics):
         "accuracy": acc,
         "roofline": roofline,
         "forms": forms,
-        "pipeline": pipeline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res))
@@ -569,6 +543,32 @@ def main():
             acc = metrics.sy2sb_errors(A0, torch.tril(A), out["tau"], w, eig=False)
         acc = {k: v for k, v in acc.items() if v is not None}
 
+    pipeline = None
+    if kind == "sy" and not args.no_pipeline:
+        # the two-stage eigenvalue pipeline the paper times after its first
+        # stage (Sec. 4.3): band -> tridiagonal, then the eigenvalues, on the
+        # band of the last timed result
+        log("bench: stage 2 and eigenvalues")
+        t2, t3 = [], []
+        for _ in range(2):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e2 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            dg, eg = br.sb2st(A, w, check=False)
+            e1.record(stream)
+            lam = br.tridiag_eigvals(dg, eg)
+            e2.record(stream)
+            torch.cuda.synchronize()
+            t2.append(e0.elapsed_time(e1))
+            t3.append(e1.elapsed_time(e2))
+        pipeline = {"stage1_ms": ms, "sb2st_ms": min(t2), "tridiag_eig_ms": min(t3),
+                    "total_ms": ms + min(t2) + min(t3)}
+        if "lam" in p:
+            ref = torch.sort(torch.as_tensor(p["lam"], dtype=torch.float64)).values
+            pipeline["eig_err_vs_known"] = float((lam.cpu() - ref).abs().max() / ref.abs().max())
+
+
     # dominant kernel: one more step with per-launch events
     log("bench: per-kernel profile step")
     restore()
@@ -646,6 +646,7 @@ def main():
         "kernels": breakdown,
         "kernels_serial": breakdown_serial,
         "forms": forms,
+        "pipeline": pipeline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res))
