@@ -237,7 +237,7 @@ struct OzDesc {
   const int8_t *PA, *PB;   // blocked planes of op(A) (M rows) and op(B) (N rows)
   const int *ea, *eb;      // exponents: ea[seg M + row], eb[seg N + col]
   int M, N, Kp, L0;        // plane columns, and where segment 1 starts
-  int kchunk;              // k range of one blockIdx.z (multiple of 64)
+  int kchunk;              // k range of one k chunk (multiple of 64)
   double *C;
   int64_t ldc;
   double alpha, beta;
@@ -248,7 +248,6 @@ struct OzDesc {
   int nI, nJ, nZ;          // tiles: row blocks, column blocks, k chunks
   const int *abort;
 };
-
 
 // 64 x 64 output tile, 4 waves as 2 x 2 (32 x 32 each: 2 x 2 blocks of 16 x 16).
 // One LDS stage buffer (56 KB) and at most 256 registers per lane, so that
@@ -265,6 +264,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_oz(OzDesc d) {
   // every (row block, column block, k chunk) with the row block fastest
   const int T = blockIdx.x;
   int i0, j0, kbeg, kend, z = 0;
+  int ib, jb;  // the tile's 64-row blocks in the planes of op(A) and op(B)
   if (EPI == E_SYR2K) {
     // J: the largest column with S(J) = J nI - J (J - 1) / 2 <= T
     const double b2 = d.nI + 0.5;
@@ -276,6 +276,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_oz(OzDesc d) {
     const int I = J + (T - S(J));
     i0 = d.c0 + I * 64;
     j0 = d.c0 + J * 64;
+    ib = I;  // (the planes start at row c0)
+    jb = J;
     kbeg = 0;
     kend = d.Kp;
   } else {
@@ -283,6 +285,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_oz(OzDesc d) {
     z = T / (d.nI * d.nJ);
     i0 = I * 64;
     j0 = J * 64;
+    ib = I;
+    jb = J;
     kbeg = z * d.kchunk;
     kend = min(d.Kp, kbeg + d.kchunk);
   }
@@ -297,8 +301,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_oz(OzDesc d) {
   typedef __attribute__((address_space(1))) const void gvoid;
   typedef __attribute__((address_space(3))) void lvoid;
   const int64_t rowblk = (int64_t)(d.Kp / 64) * kOzS * kOzBlk;  // one 64-row block, all planes
-  const int8_t *gA = d.PA + (int64_t)(i0 / 64) * rowblk + wv * 1024 + 16 * lane;
-  const int8_t *gB = d.PB + (int64_t)(j0 / 64) * rowblk + wv * 1024 + 16 * lane;
+  const int8_t *gA = d.PA + (int64_t)ib * rowblk + wv * 1024 + 16 * lane;
+  const int8_t *gB = d.PB + (int64_t)jb * rowblk + wv * 1024 + 16 * lane;
   auto issue_stage = [&](int k0) {
     int8_t *base = lds + wv * 1024;
     const int64_t kofs = (int64_t)(k0 / 64) * kOzS * kOzBlk;
@@ -516,6 +520,9 @@ int oz_gemm(int epi, const int8_t *PA, const int8_t *PB, const int *ea, const in
   d.M = M; d.N = N; d.Kp = Kp; d.L0 = L0; d.kchunk = kchunk;
   d.C = C; d.ldc = ldc; d.alpha = alpha; d.beta = beta; d.part = part;
   d.c0 = c0; d.c1 = c1; d.abort = abort;
+  // the SYR2K's planes and exponents are those of the rows from C's first
+  // (the caller offsets C, op(A) and op(B) to the column range's start)
+  if (epi == E_SYR2K && c0 != 0) return BANDRED_ERR_UNSUPPORTED;
   if (epi == E_SYR2K) {
     const int rows = M - c0, cols = c1 - c0;
     if (rows <= 0 || cols <= 0) return 0;
