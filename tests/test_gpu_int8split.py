@@ -136,6 +136,44 @@ def test_ge2gb_int8split_scaled(bandred, orc, form):
     assert err["backward"] <= 1e-14 * m, err
 
 
+@pytest.mark.parametrize("form", ["sy2sb", "ge2gb_lu"])
+def test_int8split_graph_replay_matches_eager(bandred, form):
+    """The exact-split reduction captured in a HIP graph (after one eager
+    call of the same size reserved its digit planes) and replayed three
+    times with eager work in between: every replay equals the eager result
+    bit for bit (fill kernels, no memset nodes; the row maxima the SYR2K
+    records are cleared by a kernel in the graph)."""
+    n, w, b = 700, 96, 64
+    print(f"case int8split graph {form} n={n} w={w} b={b}", flush=True)
+    A = inputs.sym_normal(n, 42) if form == "sy2sb" else inputs.ge_normal(n, n, 43)
+    A0, _ = to_device_colmajor(A, n)
+    Ad = A0.clone()
+    fn = bandred.sy2sb if form == "sy2sb" else bandred.ge2gb_lu
+    wb = (w, b) if form == "sy2sb" else (w, w)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        out_e = fn(Ad, *wb, prec="int8split", stream=s)
+    torch.cuda.synchronize()
+    ref = Ad.clone()
+    tref = [x.clone() for x in (out_e if isinstance(out_e, tuple) else (out_e,))]
+    Ad.copy_(A0)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            out_g = fn(Ad, *wb, prec="int8split", stream=s)
+    torch.cuda.synchronize()
+    tg = out_g if isinstance(out_g, tuple) else (out_g,)
+    for rep in range(3):
+        Ad.copy_(A0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()  # eager work between replays
+        assert torch.equal(Ad, ref), rep
+        assert all(torch.equal(x, y) for x, y in zip(tg, tref)), rep
+
+
 def test_sy2sb_int8split_full_size(bandred):
     """The n = 16384, w = b = 128 graded-spectrum workload in the exact-split
     form as the bench times it (look-ahead, eager calls): backward error by
