@@ -425,6 +425,19 @@ __global__ void k_tridiag_bounds(const double *dg, const double *e, int n, doubl
   }
 }
 
+// 1/x from the hardware approximation plus two Newton steps (each squares
+// the relative error): a few units in the last place, and a much shorter
+// dependence chain than a correctly rounded division, which sits on the
+// Sturm recurrence's sequential chain.  A count from slightly perturbed
+// pivots is the exact count of a tridiagonal matrix within a few ulps of
+// the given one, as with any floating-point Sturm count.
+__device__ __forceinline__ double s2_rcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+
 __global__ __launch_bounds__(256) void k_tridiag_eig(const double *dg, const double *e, int n,
                                                      const double *bounds, double *lam) {
   const int lane = threadIdx.x & 63;
@@ -443,7 +456,7 @@ __global__ __launch_bounds__(256) void k_tridiag_eig(const double *dg, const dou
     cnt += (q < 0.0);
     for (int i = 1; i < n; ++i) {
       const double ei = e[i - 1];
-      q = (dg[i] - x) - (ei * ei) / q;
+      q = (dg[i] - x) - (ei * ei) * s2_rcp(q);
       if (fabs(q) < pivmin) q = -pivmin;
       cnt += (q < 0.0);
     }
