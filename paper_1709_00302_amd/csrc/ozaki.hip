@@ -111,6 +111,15 @@ __device__ __forceinline__ void oz_stage(const OzSrc &s, int r0, int k0, int kli
   }
 }
 
+// |x| for a finite x, +Inf for NaN and +-Inf (fmax would skip a NaN): a row
+// or column with a non-finite entry gets the exponent kOzNonFinite, and every
+// result it meets is NaN, as in FP64 arithmetic.
+constexpr int kOzNonFinite = 1 << 20;
+__device__ __forceinline__ double oz_mag(double x) {
+  const double a = fabs(x);
+  return a <= 1.7976931348623157e308 ? a : __builtin_inf();
+}
+
 // largest |entry| of each row in each segment (rmax[seg rows + r]), as the
 // bits of a non-negative double (atomicMax on them orders like the values);
 // rmax is zero at launch.  A symmetric operand (one segment) visits the lower
@@ -129,7 +138,7 @@ __global__ __launch_bounds__(256) void k_oz_rowmax(OzSrc s, unsigned long long *
   unsigned long long *rm = rmax + (int64_t)seg * s.rows;
   double m = 0.0;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) m = fmax(m, fabs(t[x][16 * q + k]));
+  for (int k = 0; k < 16; ++k) m = fmax(m, oz_mag(t[x][16 * q + k]));
   m = fmax(m, __shfl_xor(m, 1));
   m = fmax(m, __shfl_xor(m, 2));
   const int r = rb * 64 + x;
@@ -138,7 +147,7 @@ __global__ __launch_bounds__(256) void k_oz_rowmax(OzSrc s, unsigned long long *
   if (sym && rb > kb) {  // column maxima (the mirrored rows)
     double c = 0.0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) c = fmax(c, fabs(t[16 * q + i][x]));
+    for (int i = 0; i < 16; ++i) c = fmax(c, oz_mag(t[16 * q + i][x]));
     c = fmax(c, __shfl_xor(c, 1));
     c = fmax(c, __shfl_xor(c, 2));
     const int rr = kb * 64 + x;
@@ -154,7 +163,9 @@ __global__ void k_oz_exps(const unsigned long long *rmax, int count, int *ex) {
   if (r >= count) return;
   const double m = __longlong_as_double((long long)rmax[r]);
   int e = 0;
-  if (m > 0.0) {
+  if (!(m <= 1.7976931348623157e308)) {
+    e = kOzNonFinite;
+  } else if (m > 0.0) {
     const double f = frexp(m, &e);  // m = f 2^e, f in [0.5, 1)
     if (f >= 127.0 / 128.0) ++e;    // then m < (127/128) 2^e
     ++e;
@@ -172,7 +183,7 @@ __device__ __forceinline__ void oz_digits4(const double *v, int e, unsigned *w) 
   unsigned zl[4], zh[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    const double r = rint(ldexp(v[c], 56 - e));
+    const double r = (e == kOzNonFinite) ? 0.0 : rint(ldexp(v[c], 56 - e));
     const double h = floor(r * 0x1p-32);
     const double l = fma(-h, 0x1p32, r);  // exact, in [0, 2^32)
     const uint64_t Y = ((uint64_t)(int64_t)(int)h << 32) + (uint64_t)(unsigned)l;
@@ -349,7 +360,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_oz(OzDesc d) {
 #pragma unroll
           for (int t = kOzS - 1; t >= 0; --t)  // pair order t + 2, smallest first
             s += (double)acc[t][a][b][e] * ldexp(1.0, -8 * (t + 2));
-          acc64[a][b][e] += ldexp(s, ea[er[a][e]] + xb);
+          const int x = ea[er[a][e]] + xb;
+          acc64[a][b][e] += (x >= kOzNonFinite / 2) ? __builtin_nan("") : ldexp(s, x);
         }
 #pragma unroll
         for (int t = 0; t < kOzS; ++t) acc[t][a][b] = v4i{0, 0, 0, 0};
@@ -436,8 +448,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm_oz(OzDesc d) {
           const double x = *c - v;
           *c = x;
           if (col >= d.rec_off) {
-            rowm[a][e] = fmax(rowm[a][e], fabs(x));
-            colm[b] = fmax(colm[b], fabs(x));
+            rowm[a][e] = fmax(rowm[a][e], oz_mag(x));
+            colm[b] = fmax(colm[b], oz_mag(x));
           }
         }
       }

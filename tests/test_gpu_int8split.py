@@ -136,6 +136,44 @@ def test_ge2gb_int8split_scaled(bandred, orc, form):
     assert err["backward"] <= 1e-14 * m, err
 
 
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+@pytest.mark.parametrize("form", ["sy2sb", "ge2gb"])
+def test_int8split_nonfinite_input_propagates(bandred, form, bad):
+    """One NaN or Inf in the trailing matrix reaches every result it takes part
+    in, as in FP64 arithmetic: a product operand's row or column holding a
+    non-finite entry gets no digits but a marker exponent, and every sum it
+    meets is NaN.  (Without the marker the entry would turn into finite digits
+    and the result would look valid.)  A NaN spreads the same way through
+    both forms' products and panels, so the NaN entries of the result sit
+    where the FP64 form puts them; an Inf turns into NaN here where FP64 may
+    keep an Inf, or a zero after a division by it, so that case checks only
+    that the result reports it.  The first panel stays finite."""
+    n, w = 300, 32
+    m = n if form == "sy2sb" else n + 40
+    print(f"case int8split non-finite {form} {m}x{n} w={w} value={bad}", flush=True)
+    A = inputs.sym_normal(n, 77) if form == "sy2sb" else inputs.ge_normal(m, n, 78)
+    A[n - 2, n - 40] = bad  # lower triangle, beyond the first panel
+    masks = {}
+    for prec in ("fp64", "int8split"):
+        Ad, _ = to_device_colmajor(A, m)
+        if form == "sy2sb":
+            out = (bandred.sy2sb(Ad, w, w, prec=prec),)
+        else:
+            out = bandred.ge2gb(Ad, w, w, prec=prec)
+        torch.cuda.synchronize()
+        Ag = Ad.cpu().numpy()
+        if form == "sy2sb":
+            Ag = np.tril(Ag)
+        masks[prec] = [~np.isfinite(Ag)] + [~np.isfinite(t.cpu().numpy()) for t in out]
+    for k, (a, b) in enumerate(zip(masks["fp64"], masks["int8split"])):
+        print(f"  output {k}: non-finite fp64 {a.sum()}  int8split {b.sum()}", flush=True)
+        if np.isnan(bad):
+            assert np.array_equal(a, b), k
+    assert masks["fp64"][0].any()
+    assert masks["int8split"][0].any()
+    assert not masks["int8split"][0][:, :w].any()
+
+
 @pytest.mark.parametrize("form", ["sy2sb", "ge2gb_lu"])
 def test_int8split_graph_replay_matches_eager(bandred, form):
     """The exact-split reduction captured in a HIP graph (after one eager
