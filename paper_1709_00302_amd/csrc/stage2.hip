@@ -123,35 +123,6 @@ struct Walk {
   }
 };
 
-// Load a rows x cols block into LDS (src(t, j), dst(t, j, value)) with every
-// global load of the thread issued before its first LDS store.
-constexpr int kS2Per = (kNbMax * kNbMax + kS2T - 1) / kS2T;
-template <class Src, class Dst>
-__device__ __forceinline__ void stage_in(int rows, int cols, Src src, Dst dst) {
-  double r[kS2Per];
-  Walk a(rows);
-#pragma unroll
-  for (int q = 0; q < kS2Per; ++q) {
-    r[q] = (a.j < cols) ? src(a.t, a.j) : 0.0;
-    a.next();
-  }
-  Walk b(rows);
-#pragma unroll
-  for (int q = 0; q < kS2Per; ++q) {
-    if (b.j < cols) dst(b.t, b.j, r[q]);
-    b.next();
-  }
-}
-
-template <class F>
-__device__ __forceinline__ void for_block(int rows, int cols, F f) {
-  Walk a(rows);
-  for (int q = 0; q < kS2Per && a.j < cols; ++q) {
-    f(a.t, a.j);
-    a.next();
-  }
-}
-
 // Band-store accesses of the bulge chasing: relaxed atomics at agent scope.
 // The sweeps hand their blocks to one another across workgroups (possibly on
 // different XCDs, whose L2 caches are not coherent with each other); with
@@ -162,6 +133,95 @@ __device__ __forceinline__ double bld(const double *p) {
 }
 __device__ __forceinline__ void bst(double *p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A rows x cols block of the band store whose element (t, j) is the matrix
+// element (r0 + t, c0 + j), at AB + (r0 + t) + (c0 + j)(ld - 1).  When rows
+// divides the workgroup (every full block for w = 32, 64, 128) a thread keeps
+// row t = tid % rows and takes the columns j = tid / rows + q dj, dj = kS2T /
+// rows: its addresses step by the uniform stride dj (ld - 1) and its row's
+// entries of v and p stay in registers.  Other shapes (the shorter blocks at
+// the end of a sweep) walk the elements in column-major order, kS2T apart.
+struct BandBlk {
+  double *AB;
+  int64_t ld;
+  int r0, c0, rows, cols;
+  __device__ __forceinline__ double *at(int t, int j) const {
+    return AB + (int64_t)(r0 + t) + (int64_t)(c0 + j) * (ld - 1);
+  }
+};
+constexpr int kS2Per = (kNbMax * kNbMax + kS2T - 1) / kS2T;  // elements per thread
+
+// dst(t, j, value) for the elements with keep(t, j), every global load of the
+// thread issued before its first LDS store.
+template <class Keep, class Dst>
+__device__ __forceinline__ void blk_load(const BandBlk &b, Keep keep, Dst dst) {
+  double r[kS2Per];
+  if (kS2T % b.rows == 0) {
+    const int t = threadIdx.x % b.rows, j0 = threadIdx.x / b.rows, dj = kS2T / b.rows;
+    const double *p = b.at(t, j0);
+    const int64_t step = (int64_t)dj * (b.ld - 1);
+#pragma unroll
+    for (int q = 0; q < kS2Per; ++q) {
+      const int j = j0 + q * dj;
+      r[q] = (j < b.cols && keep(t, j)) ? bld(p + q * step) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kS2Per; ++q) {
+      const int j = j0 + q * dj;
+      if (j < b.cols && keep(t, j)) dst(t, j, r[q]);
+    }
+    return;
+  }
+  Walk a(b.rows);
+#pragma unroll
+  for (int q = 0; q < kS2Per; ++q) {
+    r[q] = (a.j < b.cols && keep(a.t, a.j)) ? bld(b.at(a.t, a.j)) : 0.0;
+    a.next();
+  }
+  Walk c(b.rows);
+#pragma unroll
+  for (int q = 0; q < kS2Per; ++q) {
+    if (c.j < b.cols && keep(c.t, c.j)) dst(c.t, c.j, r[q]);
+    c.next();
+  }
+}
+
+// value(t, j) to the elements with keep(t, j), and with WB also to
+// blk[t][j].  value() only reads LDS; on the fast path a thread forms half of
+// its values (their LDS reads in flight together) before it stores them.
+template <bool WB, class Keep, class Val>
+__device__ __forceinline__ void blk_store(const BandBlk &b, double *blk, Keep keep, Val value) {
+  if (kS2T % b.rows == 0) {
+    const int t = threadIdx.x % b.rows, j0 = threadIdx.x / b.rows, dj = kS2T / b.rows;
+    double *p = b.at(t, j0);
+    const int64_t step = (int64_t)dj * (b.ld - 1);
+    constexpr int H = kS2Per / 2;
+#pragma unroll
+    for (int h = 0; h < kS2Per; h += H) {
+      double x[H];
+#pragma unroll
+      for (int q = 0; q < H; ++q) x[q] = value(t, min(j0 + (h + q) * dj, b.cols - 1));
+#pragma unroll
+      for (int q = 0; q < H; ++q) {
+        const int j = j0 + (h + q) * dj;
+        if (j < b.cols && keep(t, j)) {
+          if (WB) blk[t * kS2LD + j] = x[q];
+          bst(p + (h + q) * step, x[q]);
+        }
+      }
+    }
+    return;
+  }
+  Walk a(b.rows);
+  for (int q = 0; q < kS2Per && a.j < b.cols; ++q) {
+    if (keep(a.t, a.j)) {
+      const double x = value(a.t, a.j);
+      if (WB) blk[a.t * kS2LD + a.j] = x;
+      bst(b.at(a.t, a.j), x);
+    }
+    a.next();
+  }
 }
 
 // one step (s, k) of the bulge chasing.  Every block the step touches is
@@ -181,6 +241,8 @@ __device__ bool sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s, int k, bool kep
   auto ptr = [&](int r, int c) { return AB + ((int64_t)(r - c) + (int64_t)c * ld); };
   auto get = [&](int r, int c) { return bld(ptr(r, c)); };
   auto put = [&](int r, int c, double v) { bst(ptr(r, c), v); };
+  auto all = [](int, int) { return true; };
+  auto lower = [](int t, int u) { return t >= u; };
   int cx, rx, L;
   if (k == 0) {
     cx = s;
@@ -218,7 +280,7 @@ __device__ bool sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s, int k, bool kep
   if (k >= 1) {
     const int nc = w - 1, o = kept ? 1 : 0;
     if (!kept) {
-      stage_in(L, nc, [&](int t, int j) { return get(rx + t, cx + 1 + j); },
+      blk_load(BandBlk{AB, ld, rx, cx + 1, L, nc}, all,
                [&](int t, int j, double a) { blk[t * kS2LD + j] = a; });
       __syncthreads();
     }
@@ -240,21 +302,18 @@ __device__ bool sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s, int k, bool kep
       }
       __syncthreads();
     }
-    for_block(L, nc, [&](int t, int j) {
-      put(rx + t, cx + 1 + j, blk[t * kS2LD + j + o] - sh.p[j] * sh.v[t]);
+    blk_store<false>(BandBlk{AB, ld, rx, cx + 1, L, nc}, blk, all, [&](int t, int j) {
+      return blk[t * kS2LD + j + o] - sh.p[j] * sh.v[t];
     });
     __syncthreads();
   }
   // (3) the diagonal block R x R from both sides: p = tau D v,
   //     q = p - (tau p^T v / 2) v, D -= v q^T + q v^T (lower part stored;
   //     the block is mirrored in LDS)
-  stage_in(L, L, [&](int t, int u) { return t >= u ? get(rx + t, rx + u) : 0.0; },
-           [&](int t, int u, double a) {
-             if (t >= u) {
-               blk[t * kS2LD + u] = a;
-               blk[u * kS2LD + t] = a;
-             }
-           });
+  blk_load(BandBlk{AB, ld, rx, rx, L, L}, lower, [&](int t, int u, double a) {
+    blk[t * kS2LD + u] = a;
+    blk[u * kS2LD + t] = a;
+  });
   __syncthreads();
   blk_matvec(sh, 0, L, L, tau, sh.p);  // p = tau D v
   const double pt = tid < L ? sh.p[tid] : 0.0;
@@ -262,8 +321,8 @@ __device__ bool sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s, int k, bool kep
   const double Kc = 0.5 * tau * pv;
   if (tid < L) sh.p[tid] = pt - Kc * sh.v[tid];  // q
   __syncthreads();
-  for_block(L, L, [&](int t, int u) {
-    if (t >= u) put(rx + t, rx + u, blk[t * kS2LD + u] - (sh.v[t] * sh.p[u] + sh.p[t] * sh.v[u]));
+  blk_store<false>(BandBlk{AB, ld, rx, rx, L, L}, blk, lower, [&](int t, int u) {
+    return blk[t * kS2LD + u] - (sh.v[t] * sh.p[u] + sh.p[t] * sh.v[u]);
   });
   __syncthreads();
   // (4) the block below, rows rx+w .. rx+2w-1, from the right:
@@ -271,17 +330,14 @@ __device__ bool sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s, int k, bool kep
   const int r2 = rx + w;
   const int m2 = min(rx + 2 * w, n) - r2;
   if (m2 > 0) {
-    stage_in(m2, L, [&](int i, int u) { return get(r2 + i, rx + u); },
+    blk_load(BandBlk{AB, ld, r2, rx, m2, L}, all,
              [&](int i, int u, double a) { blk[i * kS2LD + u] = a; });
     __syncthreads();
     blk_matvec(sh, 0, m2, L, tau, sh.p);  // y = tau B v
     // updated in place and written back; the block stays in LDS for the
     // next step of this sweep
-    for_block(m2, L, [&](int i, int u) {
-      const double a = blk[i * kS2LD + u] - sh.p[i] * sh.v[u];
-      blk[i * kS2LD + u] = a;
-      put(r2 + i, rx + u, a);
-    });
+    blk_store<true>(BandBlk{AB, ld, r2, rx, m2, L}, blk, all,
+                    [&](int i, int u) { return blk[i * kS2LD + u] - sh.p[i] * sh.v[u]; });
     return true;
   }
   return false;
