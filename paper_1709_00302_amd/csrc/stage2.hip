@@ -152,11 +152,11 @@ struct BandBlk {
 };
 constexpr int kS2Per = (kNbMax * kNbMax + kS2T - 1) / kS2T;  // elements per thread
 
-// dst(t, j, value) for the elements with keep(t, j), every global load of the
-// thread issued before its first LDS store.
-template <class Keep, class Dst>
-__device__ __forceinline__ void blk_load(const BandBlk &b, Keep keep, Dst dst) {
-  double r[kS2Per];
+// The loads of a block in two halves, so that other work can run while they
+// are in flight: blk_fetch issues the loads of the elements with keep(t, j)
+// into r[], blk_place hands the arrived values to dst(t, j, value).
+template <class Keep>
+__device__ __forceinline__ void blk_fetch(const BandBlk &b, Keep keep, double (&r)[kS2Per]) {
   if (kS2T % b.rows == 0) {
     const int t = threadIdx.x % b.rows, j0 = threadIdx.x / b.rows, dj = kS2T / b.rows;
     const double *p = b.at(t, j0);
@@ -166,11 +166,6 @@ __device__ __forceinline__ void blk_load(const BandBlk &b, Keep keep, Dst dst) {
       const int j = j0 + q * dj;
       r[q] = (j < b.cols && keep(t, j)) ? bld(p + q * step) : 0.0;
     }
-#pragma unroll
-    for (int q = 0; q < kS2Per; ++q) {
-      const int j = j0 + q * dj;
-      if (j < b.cols && keep(t, j)) dst(t, j, r[q]);
-    }
     return;
   }
   Walk a(b.rows);
@@ -179,12 +174,31 @@ __device__ __forceinline__ void blk_load(const BandBlk &b, Keep keep, Dst dst) {
     r[q] = (a.j < b.cols && keep(a.t, a.j)) ? bld(b.at(a.t, a.j)) : 0.0;
     a.next();
   }
+}
+template <class Keep, class Dst>
+__device__ __forceinline__ void blk_place(const BandBlk &b, Keep keep, const double (&r)[kS2Per],
+                                          Dst dst) {
+  if (kS2T % b.rows == 0) {
+    const int t = threadIdx.x % b.rows, j0 = threadIdx.x / b.rows, dj = kS2T / b.rows;
+#pragma unroll
+    for (int q = 0; q < kS2Per; ++q) {
+      const int j = j0 + q * dj;
+      if (j < b.cols && keep(t, j)) dst(t, j, r[q]);
+    }
+    return;
+  }
   Walk c(b.rows);
 #pragma unroll
   for (int q = 0; q < kS2Per; ++q) {
     if (c.j < b.cols && keep(c.t, c.j)) dst(c.t, c.j, r[q]);
     c.next();
   }
+}
+template <class Keep, class Dst>
+__device__ __forceinline__ void blk_load(const BandBlk &b, Keep keep, Dst dst) {
+  double r[kS2Per];
+  blk_fetch(b, keep, r);
+  blk_place(b, keep, r, dst);
 }
 
 // value(t, j) to the elements with keep(t, j), and with WB also to
@@ -234,7 +248,8 @@ __device__ __forceinline__ void blk_store(const BandBlk &b, double *blk, Keep ke
 // below row rx + w)
 // Returns whether the step left its own block below in blk (false when it
 // ends early: a trivial reflector, or no block below).
-__device__ bool sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s, int k, bool kept) {
+__device__ __forceinline__ bool sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s, int k,
+                                           bool kept) {
   const int n = d.n, w = d.w, tid = threadIdx.x;
   const int64_t ld = d.ldab;
   double *AB = d.AB;
@@ -274,6 +289,17 @@ __device__ bool sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s, int k, bool kep
     put(rx + tid, cx, (tid == 0) ? beta : 0.0);
   }
   __syncthreads();
+  // The diagonal block (rows and columns rx .. rx+L-1) and the block below
+  // (rows rx+w .., columns rx .. rx+L-1) are final from the start of the
+  // step: the steps of the previous sweep that write them have finished,
+  // later sweeps wait for this one, and the stores this step makes before
+  // loading them go to other rows or columns.  So their loads are issued
+  // early, each hidden behind the phase before it.
+  const BandBlk bd{AB, ld, rx, rx, L, L};
+  const int r2 = rx + w;
+  const int m2 = min(rx + 2 * w, n) - r2;
+  const BandBlk bb{AB, ld, r2, rx, m2, L};
+  double rd[kS2Per], rb[kS2Per];
   // (2) the rest of the bulge block, rows rx .. rx+L-1, columns cx+1 ..
   //     cx+w-1, from the left: B(rx + t, cx + 1 + j) = blk[t][j + o] with
   //     o = 1 for the kept block (its column 0 is column cx), else 0
@@ -284,6 +310,7 @@ __device__ bool sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s, int k, bool kep
                [&](int t, int j, double a) { blk[t * kS2LD + j] = a; });
       __syncthreads();
     }
+    blk_fetch(bd, lower, rd);
     // z_j = tau v^T blk(:, j): the columns o .. o + nc - 1 of blk
     {
       const int g = tid / kNbMax, xj = tid % kNbMax;
@@ -306,37 +333,37 @@ __device__ bool sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s, int k, bool kep
       return blk[t * kS2LD + j + o] - sh.p[j] * sh.v[t];
     });
     __syncthreads();
+  } else {
+    blk_fetch(bd, lower, rd);
   }
   // (3) the diagonal block R x R from both sides: p = tau D v,
   //     q = p - (tau p^T v / 2) v, D -= v q^T + q v^T (lower part stored;
   //     the block is mirrored in LDS)
-  blk_load(BandBlk{AB, ld, rx, rx, L, L}, lower, [&](int t, int u, double a) {
+  blk_place(bd, lower, rd, [&](int t, int u, double a) {
     blk[t * kS2LD + u] = a;
     blk[u * kS2LD + t] = a;
   });
   __syncthreads();
+  if (m2 > 0) blk_fetch(bb, all, rb);
   blk_matvec(sh, 0, L, L, tau, sh.p);  // p = tau D v
   const double pt = tid < L ? sh.p[tid] : 0.0;
   const double pv = block_sum(tid < L ? pt * sh.v[tid] : 0.0, sh.red);
   const double Kc = 0.5 * tau * pv;
   if (tid < L) sh.p[tid] = pt - Kc * sh.v[tid];  // q
   __syncthreads();
-  blk_store<false>(BandBlk{AB, ld, rx, rx, L, L}, blk, lower, [&](int t, int u) {
+  blk_store<false>(bd, blk, lower, [&](int t, int u) {
     return blk[t * kS2LD + u] - (sh.v[t] * sh.p[u] + sh.p[t] * sh.v[u]);
   });
   __syncthreads();
   // (4) the block below, rows rx+w .. rx+2w-1, from the right:
   //     blk[i][u] = B(r2 + i, rx + u)
-  const int r2 = rx + w;
-  const int m2 = min(rx + 2 * w, n) - r2;
   if (m2 > 0) {
-    blk_load(BandBlk{AB, ld, r2, rx, m2, L}, all,
-             [&](int i, int u, double a) { blk[i * kS2LD + u] = a; });
+    blk_place(bb, all, rb, [&](int i, int u, double a) { blk[i * kS2LD + u] = a; });
     __syncthreads();
     blk_matvec(sh, 0, m2, L, tau, sh.p);  // y = tau B v
     // updated in place and written back; the block stays in LDS for the
     // next step of this sweep
-    blk_store<true>(BandBlk{AB, ld, r2, rx, m2, L}, blk, all,
+    blk_store<true>(bb, blk, all,
                     [&](int i, int u) { return blk[i * kS2LD + u] - sh.p[i] * sh.v[u]; });
     return true;
   }
