@@ -21,19 +21,21 @@
 // Sweeps run concurrently: one persistent workgroup per sweep at a time,
 // sweeps claimed in increasing order from an atomic counter.  Step k >= 1 of
 // sweep s touches the elements (r, c) with r in s+1+kw .. s+(k+2)w and c in
-// s+1+(k-1)w .. s+(k+1)w (step 0: rows s+1 .. s+2w, columns s .. s+w); step
-// k' of sweep s+1 meets these only for k in k'-1 .. k'+2, so it may start once
-// sweep s-1 has finished k'+3 steps, after which no later step of sweep s
-// touches the same elements: every element sees the operations of the
-// sequential order, in that order.  The waits are bounded (wall
-// clock), and a workgroup that gives up raises an abort flag that releases
-// every other one.
+// s+1+(k-1)w .. s+(k+1)w (step 0: rows s+1 .. s+2w, columns s .. s+w): its
+// rows s+1+kw .. s+(k+1)w (the reflector's column, the bulge block and the
+// diagonal block) meet only steps k-1 .. k+1 of sweep s-1, its block below
+// (rows s+1+(k+1)w ..) steps k .. k+2.  So step k begins once sweep s-1 has
+// finished k+2 steps and loads its block below once it has finished k+3;
+// meanwhile sweep s-1's later steps stay below row s+(k+2)w, clear of
+// everything step k touches until then, so every element sees the
+// operations of the sequential order, in that order.  The waits are bounded
+// (wall clock), and a workgroup that gives up raises an abort flag that
+// releases every other one.
 #include "common.hpp"
 
 namespace br {
 
 constexpr int kS2T = 512;      // threads of the bulge-chasing workgroup (8 waves)
-constexpr int kS2Lag = 3;      // steps sweep s-1 must be ahead of sweep s
 constexpr int kS2LD = kNbMax + 1;  // row stride of the LDS block (odd: no bank conflicts)
 
 struct Sb2stDesc {
@@ -238,6 +240,38 @@ __device__ __forceinline__ void blk_store(const BandBlk &b, double *blk, Keep ke
   }
 }
 
+__device__ __forceinline__ long long s2_ticks() { return (long long)wall_clock64(); }
+
+// Wait, with the whole workgroup, until sweep s-1 has finished `need` steps:
+// thread 0 polls the progress word relaxed and acquires once at agent scope,
+// and the barrier orders the other threads after it.  False when the wait
+// gave up (its time limit, or another workgroup's abort).
+__device__ __forceinline__ bool wait_prev(const Sb2stDesc &d, S2Lds &sh, int s, int need) {
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const long long t0 = s2_ticks();
+    while (__hip_atomic_load(d.progress + (s - 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+           need) {
+      if (__hip_atomic_load(d.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        ok = 0;
+        break;
+      }
+      if (s2_ticks() - t0 > d.timeout_ticks) {
+        __hip_atomic_store(d.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(d.status, (int)BANDRED_ERR_TIMEOUT, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    sh.go = ok;
+  }
+  __syncthreads();
+  return sh.go != 0;
+}
+
 // one step (s, k) of the bulge chasing.  Every block the step touches is
 // brought into LDS with coalesced loads (a column of a block is a contiguous
 // piece of a band-store column), updated there and written back.
@@ -246,10 +280,13 @@ __device__ __forceinline__ void blk_store(const BandBlk &b, double *blk, Keep ke
 // block, which no other sweep changes in between (the earlier sweep's steps
 // that meet them finished before step k - 1 began, the later ones start
 // below row rx + w)
+// need_below: progress of sweep s-1 required before the block below is
+// loaded (0: none).
 // Returns whether the step left its own block below in blk (false when it
-// ends early: a trivial reflector, or no block below).
+// ends early: a trivial reflector, no block below, or a wait that gave up,
+// which leaves sh.go = 0).
 __device__ __forceinline__ bool sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s, int k,
-                                           bool kept) {
+                                           bool kept, int need_below) {
   const int n = d.n, w = d.w, tid = threadIdx.x;
   const int64_t ld = d.ldab;
   double *AB = d.AB;
@@ -343,7 +380,11 @@ __device__ __forceinline__ bool sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s,
     blk[t * kS2LD + u] = a;
     blk[u * kS2LD + t] = a;
   });
-  __syncthreads();
+  if (m2 > 0 && need_below > 0) {
+    if (!wait_prev(d, sh, s, need_below)) return false;  // its barrier ends the placement
+  } else {
+    __syncthreads();
+  }
   if (m2 > 0) blk_fetch(bb, all, rb);
   blk_matvec(sh, 0, L, L, tau, sh.p);  // p = tau D v
   const double pt = tid < L ? sh.p[tid] : 0.0;
@@ -370,13 +411,14 @@ __device__ __forceinline__ bool sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s,
   return false;
 }
 
-__device__ __forceinline__ long long s2_ticks() { return (long long)wall_clock64(); }
-
 __global__ __launch_bounds__(kS2T) void k_sb2st(Sb2stDesc d) {
   __shared__ S2Lds sh;
   const int tid = threadIdx.x;
   for (;;) {
-    if (tid == 0) sh.sweep = (int)atomicAdd(d.sweep_ctr, 1u);
+    if (tid == 0) {
+      sh.sweep = (int)atomicAdd(d.sweep_ctr, 1u);
+      sh.go = 1;
+    }
     __syncthreads();
     const int s = sh.sweep;
     __syncthreads();
@@ -385,39 +427,12 @@ __global__ __launch_bounds__(kS2T) void k_sb2st(Sb2stDesc d) {
     const int Kp = (s > 0) ? sweep_steps(d.n, d.w, s - 1) : 0;
     bool kept = false;  // blk holds the block below of the previous step
     for (int k = 0; k < K; ++k) {
-      if (s > 0) {
-        if (tid == 0) {
-          const int need = min(k + kS2Lag, Kp);
-          int ok = 1;
-          const long long t0 = s2_ticks();
-          // relaxed polling; one acquire fence once the word is reached
-          while (__hip_atomic_load(d.progress + (s - 1), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT) < need) {
-            if (__hip_atomic_load(d.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-              ok = 0;
-              break;
-            }
-            if (s2_ticks() - t0 > d.timeout_ticks) {
-              __hip_atomic_store(d.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              __hip_atomic_store(d.status, (int)BANDRED_ERR_TIMEOUT, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT);
-              ok = 0;
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-          }
-          // acquire (agent scope) once, by this thread; the workgroup barrier
-          // below orders the other threads after it
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-          sh.go = ok;
-        }
-        __syncthreads();
-        if (!sh.go) return;
-      }
-      kept = sb2st_step(d, sh, s, k, kept && k >= 1);
+      if (s > 0 && !wait_prev(d, sh, s, min(k + 2, Kp))) return;
+      kept = sb2st_step(d, sh, s, k, kept && k >= 1, (s > 0) ? min(k + 3, Kp) : 0);
       // publish: every thread's stores, then the progress word
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __syncthreads();
+      if (!sh.go) return;  // the wait inside the step gave up
       if (tid == 0)
         __hip_atomic_store(d.progress + s, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }

@@ -118,3 +118,30 @@ def test_stage2_argument_errors(bandred):
     assert bandred.bandred_sb2st(4, 1, p, 3, p, p) == -4
     assert bandred.bandred_tridiag_eigvals(-1, p, p, p) == -1
     assert bandred.bandred_tridiag_eigvals(4, p, None, p) == -3
+
+
+def test_sb2st_timeout_is_reported(bandred):
+    """The bulge chasing's inter-workgroup waits (before a step, and before a
+    step loads its block below) bounded to one microsecond from the host: the
+    first sweep that waits longer gives up and raises the abort flag, every
+    other workgroup returns at its next wait, and the call reports
+    BANDRED_ERR_TIMEOUT.  Nothing faults or hangs.  With the default bound the
+    same call succeeds and preserves the band's Frobenius norm."""
+    n, w = 2000, 32
+    A = inputs.sym_normal(n, 812)  # only the band 0 <= i - j <= w is read
+    Ad, _ = to_device_colmajor(A, n)
+    print(f"case sb2st timeout n={n} w={w}", flush=True)
+    assert bandred.bandred_set_wait_limit_us(1.0) == 0
+    try:
+        with pytest.raises(bandred.BandredError) as ei:
+            bandred.sb2st(Ad, w)
+        assert ei.value.code == 4  # BANDRED_ERR_TIMEOUT
+    finally:
+        assert bandred.bandred_set_wait_limit_us(0.0) == 0
+    d, e = bandred.sb2st(Ad, w)
+    torch.cuda.synchronize()
+    assert bandred.bandred_status(None) == 0
+    B = _band_dense(A, w)
+    dh, eh = d.cpu().numpy(), e.cpu().numpy()
+    fro = np.sqrt(np.sum(dh ** 2) + 2 * np.sum(eh ** 2))
+    assert abs(fro - np.linalg.norm(B)) <= 1e-14 * n * np.linalg.norm(B)
