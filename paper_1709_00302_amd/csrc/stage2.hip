@@ -484,13 +484,16 @@ int launch_sb2st(const double *A, int64_t lda, int n, int w, double *AB, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// Eigenvalues of the tridiagonal matrix: multisection on Sturm counts.  One
-// wave per eigenvalue index k: the 64 lanes count the eigenvalues below 64
-// points spread evenly inside the current interval [a, b] (which holds
-// eigenvalue k), and the interval shrinks to the subinterval where the count
-// passes k, 65 times narrower per round, until a and b are adjacent doubles
-// or within 2 eps of the matrix's Gershgorin scale.  The count is the number
-// of negative pivots of LDL^T of T - x I (a zero pivot counts as -pivmin).
+// Eigenvalues of the tridiagonal matrix: multisection on Sturm counts.  A
+// group of G lanes of a wave per eigenvalue index k: the lanes count the
+// eigenvalues below G points spread evenly inside the current interval [a, b]
+// (which holds eigenvalue k), and the interval shrinks to the subinterval
+// where the count passes k, G + 1 times narrower per round, until a and b are
+// adjacent doubles or within 2 eps of the matrix's Gershgorin scale.  The
+// count is the number of negative pivots of LDL^T of T - x I (a zero pivot
+// counts as -pivmin).  A wider section takes fewer rounds but more counts in
+// all (G / log2(G+1) per bit of the result); G is the smallest that still
+// gives the chip about two waves per SIMD.
 // ---------------------------------------------------------------------------
 __global__ void k_tridiag_bounds(const double *dg, const double *e, int n, double *bounds) {
   __shared__ double slo[256], shi[256], se2[256];
@@ -536,17 +539,19 @@ __device__ __forceinline__ double s2_rcp(double x) {
   return y;
 }
 
+template <int G>
 __global__ __launch_bounds__(256) void k_tridiag_eig(const double *dg, const double *e, int n,
                                                      const double *bounds, double *lam) {
   const int lane = threadIdx.x & 63;
-  const int k = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
-  if (k >= n) return;
+  const int j = lane % G, g0 = lane - j;  // this lane's point, its group's first lane
+  const int k = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G);
+  if (k >= n) return;  // whole groups (G divides 64)
   double a = bounds[0], b = bounds[1];
   const double pivmin = bounds[2];
   const double tol = 2.0 * 2.220446049250313e-16 * bounds[3];
   for (int round = 0; round < 64; ++round) {
-    if (b - a <= tol) break;
-    const double x = a + (b - a) * (double)(lane + 1) * (1.0 / 65.0);
+    if (b - a <= tol) break;  // a and b are uniform in the group
+    const double x = a + (b - a) * (double)(j + 1) * (1.0 / (G + 1));
     // Sturm count below x
     int cnt = 0;
     double q = dg[0] - x;
@@ -558,18 +563,19 @@ __global__ __launch_bounds__(256) void k_tridiag_eig(const double *dg, const dou
       if (fabs(q) < pivmin) q = -pivmin;
       cnt += (q < 0.0);
     }
-    // first point whose count exceeds k: eigenvalue k lies below it
+    // first point of the group whose count exceeds k: eigenvalue k lies below it
     const unsigned long long above = __ballot(cnt > k);
-    const int f = above ? __builtin_ctzll(above) : 64;
-    const double xf = __shfl(x, f < 64 ? f : 63);
-    const double xp = __shfl(x, f > 0 ? f - 1 : 0);
+    const unsigned long long mine = (G == 64) ? above : (above >> g0) & ((1ull << (G & 63)) - 1);
+    const int f = mine ? __builtin_ctzll(mine) : G;
+    const double xf = __shfl(x, g0 + (f < G ? f : G - 1));
+    const double xp = __shfl(x, g0 + (f > 0 ? f - 1 : 0));
     const double na = (f > 0) ? xp : a;
-    const double nb = (f < 64) ? xf : b;
+    const double nb = (f < G) ? xf : b;
     if (na == a && nb == b) break;  // no progress: a and b (nearly) adjacent
     a = na;
     b = nb;
   }
-  if (lane == 0) lam[k] = 0.5 * (a + b);
+  if (j == 0) lam[k] = 0.5 * (a + b);
 }
 
 int launch_tridiag_eig(const double *dg, const double *e, int n, double *bounds, double *lam,
@@ -577,9 +583,17 @@ int launch_tridiag_eig(const double *dg, const double *e, int n, double *bounds,
   if (n <= 0) return 0;
   hipLaunchKernelGGL(k_tridiag_bounds, dim3(1), dim3(256), 0, s, dg, e, n, bounds);
   BR_HIP_CHECK(hipGetLastError());
-  const int64_t threads = (int64_t)n * 64;
-  hipLaunchKernelGGL(k_tridiag_eig, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, dg,
-                     e, n, (const double *)bounds, lam);
+  // lanes per eigenvalue: about two waves per SIMD of 256 CUs from n G lanes
+  // (measured at n = 16384 and 8192: one wave per SIMD leaves the counts'
+  // latency exposed, four make the wider sections' extra counts cost more)
+  const int G = (n >= 16384) ? 8 : (n >= 8192) ? 16 : (n >= 4096) ? 32 : 64;
+  const int64_t threads = (int64_t)n * G;
+  const dim3 grid((unsigned)((threads + 255) / 256));
+  const double *bd = bounds;
+  if (G == 8) hipLaunchKernelGGL(k_tridiag_eig<8>, grid, dim3(256), 0, s, dg, e, n, bd, lam);
+  else if (G == 16) hipLaunchKernelGGL(k_tridiag_eig<16>, grid, dim3(256), 0, s, dg, e, n, bd, lam);
+  else if (G == 32) hipLaunchKernelGGL(k_tridiag_eig<32>, grid, dim3(256), 0, s, dg, e, n, bd, lam);
+  else hipLaunchKernelGGL(k_tridiag_eig<64>, grid, dim3(256), 0, s, dg, e, n, bd, lam);
   BR_HIP_CHECK(hipGetLastError());
   return 0;
 }

@@ -63,7 +63,8 @@ def test_sb2st_tridiagonal_input_is_exact(bandred):
 
 
 @pytest.mark.parametrize("kind,n", [("random", 1), ("random", 2), ("random", 600), ("random", 2049),
-                                    ("toeplitz", 500), ("kac", 300), ("diagonal", 100)])
+                                    ("random", 4096), ("toeplitz", 500), ("kac", 300),
+                                    ("diagonal", 100)])
 def test_tridiag_eigvals_matches_oracle(bandred, orc, kind, n):
     print(f"case tridiag eig {kind} n={n}", flush=True)
     g = np.random.default_rng(n)
@@ -90,6 +91,25 @@ def test_tridiag_eigvals_matches_oracle(bandred, orc, kind, n):
         assert np.abs(got - np.sort(2 - 2 * np.cos(k * np.pi / (n + 1)))).max() <= 1e-14 * n * 4
     if kind == "kac":
         assert np.abs(got - np.arange(-(n - 1), n, 2)).max() <= 1e-14 * n * n
+
+
+@pytest.mark.parametrize("n", [2048, 4096, 8192, 16384])
+def test_tridiag_eigvals_closed_forms_large(bandred, n):
+    """The section narrows as n grows (64, 32, 16 and 8 lanes per eigenvalue
+    at these orders): the second-difference matrix (eigenvalues 2 - 2 cos(k pi /
+    (n + 1))) and the Kac matrix (eigenvalues -(n-1), -(n-3), .., n-1)."""
+    print(f"case tridiag eig closed forms n={n}", flush=True)
+    k = np.arange(1, n + 1)
+    d, e = 2.0 * np.ones(n), -np.ones(n - 1)
+    lam = bandred.tridiag_eigvals(torch.from_numpy(d).cuda(), torch.from_numpy(e).cuda())
+    i = np.arange(1, n)
+    lam2 = bandred.tridiag_eigvals(torch.zeros(n, dtype=torch.float64, device="cuda"),
+                                   torch.from_numpy(np.sqrt(i * (n - i))).cuda())
+    torch.cuda.synchronize()
+    got, got2 = lam.cpu().numpy(), lam2.cpu().numpy()
+    assert np.all(np.diff(got) >= 0) and np.all(np.diff(got2) >= 0)
+    assert np.abs(got - np.sort(2 - 2 * np.cos(k * np.pi / (n + 1)))).max() <= 1e-14 * n * 4
+    assert np.abs(got2 - np.arange(-(n - 1), n, 2)).max() <= 1e-14 * n * n
 
 
 def test_pipeline_known_spectrum(bandred):
