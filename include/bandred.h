@@ -215,8 +215,9 @@ BANDRED_API int bandred_sb2st(int64_t n, int64_t w, const double *A, int64_t lda
 
 /* All eigenvalues of the symmetric tridiagonal matrix with diagonal d (n
  * entries) and subdiagonal e (n-1 entries), ascending, into lam (n
- * entries); all device pointers.  Bisection on Sturm counts, accurate to a
- * few units of 2 eps times the Gershgorin bound of |T|.  Args: n (1), d (2),
+ * entries); all device pointers.  Multisection (bisection with several
+ * points per round) on Sturm counts, accurate to a few units of 2 eps times
+ * the Gershgorin bound of |T|.  Args: n (1), d (2),
  * e (3), lam (4), stream (5).  Asynchronous. */
 BANDRED_API int bandred_tridiag_eigvals(int64_t n, const double *d, const double *e, double *lam,
                             void *stream);
