@@ -63,9 +63,10 @@ typedef enum {
                                  inner dimension the error is below 2^-49 of the product
                                  of the row's and the column's largest entries, under the
                                  worst-case error of an FP64 dot product.  Rank-2k updates
-                                 scale their two halves apart.  Not in the paper (which
-                                 is FP64 throughout).  Work space grows by about
-                                 7 (n + 2w) n bytes (SY2SB; m and n for GE2GB) */
+                                 scale their two halves apart.  A row or column holding a
+                                 NaN or Inf makes every sum it enters NaN.  Not in the
+                                 paper (which is FP64 throughout).  Work space grows by
+                                 about 7 (n + 2w) n bytes (SY2SB; m and n for GE2GB) */
 } bandred_prec_t;
 
 /* Optional knobs for the _ex entry points (pass NULL for defaults). */
