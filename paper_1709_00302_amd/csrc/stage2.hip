@@ -426,9 +426,18 @@ __global__ __launch_bounds__(kS2T) void k_sb2st(Sb2stDesc d) {
     const int K = sweep_steps(d.n, d.w, s);
     const int Kp = (s > 0) ? sweep_steps(d.n, d.w, s - 1) : 0;
     bool kept = false;  // blk holds the block below of the previous step
+    int have = 0;       // progress of sweep s-1 this workgroup has waited for
     for (int k = 0; k < K; ++k) {
-      if (s > 0 && !wait_prev(d, sh, s, min(k + 2, Kp))) return;
-      kept = sb2st_step(d, sh, s, k, kept && k >= 1, (s > 0) ? min(k + 3, Kp) : 0);
+      // a step that loaded its block below has waited for min(k + 2, Kp)
+      // steps already: the wait before the next step is then not repeated
+      const int need = min(k + 2, Kp);
+      if (s > 0 && have < need) {
+        if (!wait_prev(d, sh, s, need)) return;
+        have = need;
+      }
+      const int need_below = (s > 0) ? min(k + 3, Kp) : 0;
+      kept = sb2st_step(d, sh, s, k, kept && k >= 1, need_below);
+      if (kept) have = max(have, need_below);  // it waited before its block below
       // publish: every thread's stores, then the progress word
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __syncthreads();
