@@ -24,13 +24,15 @@
 // s+1+(k-1)w .. s+(k+1)w (step 0: rows s+1 .. s+2w, columns s .. s+w): its
 // rows s+1+kw .. s+(k+1)w (the reflector's column, the bulge block and the
 // diagonal block) meet only steps k-1 .. k+1 of sweep s-1, its block below
-// (rows s+1+(k+1)w ..) steps k .. k+2.  So step k begins once sweep s-1 has
-// finished k+2 steps and loads its block below once it has finished k+3;
-// meanwhile sweep s-1's later steps stay below row s+(k+2)w, clear of
-// everything step k touches until then, so every element sees the
-// operations of the sequential order, in that order.  The waits are bounded
-// (wall clock), and a workgroup that gives up raises an abort flag that
-// releases every other one.
+// (rows s+1+(k+1)w ..) steps k .. k+2.  A step publishes itself once its rows
+// s+1+kw .. s+(k+1)w are stored, before it updates its block below (whose
+// stores the next step's publication covers; a sweep's last step has no
+// block below).  So step k begins once sweep s-1 has published k+2 steps and
+// loads its block below once it has published k+3; meanwhile sweep s-1's
+// later work stays below row s+(k+2)w, clear of everything step k touches
+// until then, so every element sees the operations of the sequential order,
+// in that order.  The waits are bounded (wall clock), and a workgroup that
+// gives up raises an abort flag that releases every other one.
 #include "common.hpp"
 
 namespace br {
@@ -282,11 +284,16 @@ __device__ __forceinline__ bool wait_prev(const Sb2stDesc &d, S2Lds &sh, int s, 
 // below row rx + w)
 // need_below: progress of sweep s-1 required before the block below is
 // loaded (0: none).
-// Returns whether the step left its own block below in blk (false when it
-// ends early: a trivial reflector, no block below, or a wait that gave up,
-// which leaves sh.go = 0).
-__device__ __forceinline__ bool sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s, int k,
-                                           bool kept, int need_below) {
+// The step publishes itself (progress of sweep s = k + 1) as soon as its rows
+// rx .. rx+L-1 are stored, before it updates the block below: a step of the
+// next sweep waits only on such rows and on the blocks below of earlier steps,
+// whose stores the same release covers (and a sweep's last step has no block
+// below).  Returns kS2Kept when the step left its own block below in blk, and
+// kS2Published once it has published; 0 when it ended early (a trivial
+// reflector, or a wait that gave up, which leaves sh.go = 0).
+constexpr int kS2Kept = 1, kS2Published = 2;
+__device__ __forceinline__ int sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s, int k,
+                                          bool kept, int need_below) {
   const int n = d.n, w = d.w, tid = threadIdx.x;
   const int64_t ld = d.ldab;
   double *AB = d.AB;
@@ -305,7 +312,7 @@ __device__ __forceinline__ bool sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s,
     rx = s + 1 + k * w;
     L = min(w, n - rx);
   }
-  if (L < 2) return false;
+  if (L < 2) return 0;
   double *blk = sh.blk;
   // (1) the reflector that annihilates column cx below row rx
   double x = 0.0;
@@ -315,7 +322,7 @@ __device__ __forceinline__ bool sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s,
   }
   const double sig2 = block_sum(tid >= 1 && tid < L ? x * x : 0.0, sh.red);
   const double alpha = sh.v[0];
-  if (sig2 == 0.0) return false;  // H = I
+  if (sig2 == 0.0) return 0;  // H = I
   const double nrm = sqrt(alpha * alpha + sig2);
   const double beta = (alpha < 0.0) ? nrm : -nrm;
   const double tau = (beta - alpha) / beta;
@@ -381,7 +388,7 @@ __device__ __forceinline__ bool sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s,
     blk[u * kS2LD + t] = a;
   });
   if (m2 > 0 && need_below > 0) {
-    if (!wait_prev(d, sh, s, need_below)) return false;  // its barrier ends the placement
+    if (!wait_prev(d, sh, s, need_below)) return 0;  // its barrier ends the placement
   } else {
     __syncthreads();
   }
@@ -395,7 +402,11 @@ __device__ __forceinline__ bool sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s,
   blk_store<false>(bd, blk, lower, [&](int t, int u) {
     return blk[t * kS2LD + u] - (sh.v[t] * sh.p[u] + sh.p[t] * sh.v[u]);
   });
+  // rows rx .. rx+L-1 are done: every thread's stores, then the progress word
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
+  if (tid == 0)
+    __hip_atomic_store(d.progress + s, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   // (4) the block below, rows rx+w .. rx+2w-1, from the right:
   //     blk[i][u] = B(r2 + i, rx + u)
   if (m2 > 0) {
@@ -406,9 +417,9 @@ __device__ __forceinline__ bool sb2st_step(const Sb2stDesc &d, S2Lds &sh, int s,
     // next step of this sweep
     blk_store<true>(bb, blk, all,
                     [&](int i, int u) { return blk[i * kS2LD + u] - sh.p[i] * sh.v[u]; });
-    return true;
+    return kS2Kept | kS2Published;
   }
-  return false;
+  return kS2Published;
 }
 
 __global__ __launch_bounds__(kS2T) void k_sb2st(Sb2stDesc d) {
@@ -436,14 +447,19 @@ __global__ __launch_bounds__(kS2T) void k_sb2st(Sb2stDesc d) {
         have = need;
       }
       const int need_below = (s > 0) ? min(k + 3, Kp) : 0;
-      kept = sb2st_step(d, sh, s, k, kept && k >= 1, need_below);
+      const int st = sb2st_step(d, sh, s, k, kept && k >= 1, need_below);
+      kept = (st & kS2Kept) != 0;
       if (kept) have = max(have, need_below);  // it waited before its block below
-      // publish: every thread's stores, then the progress word
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __syncthreads();
-      if (!sh.go) return;  // the wait inside the step gave up
-      if (tid == 0)
-        __hip_atomic_store(d.progress + s, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (st & kS2Published) {
+        __syncthreads();  // the next step reads the block below that blk now holds
+      } else {
+        // a step that ended early: every thread's stores, then the progress word
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (!sh.go) return;  // the wait inside the step gave up
+        if (tid == 0)
+          __hip_atomic_store(d.progress + s, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
   }
 }
