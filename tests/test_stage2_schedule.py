@@ -5,10 +5,11 @@ s tridiagonal in steps k = 0 .. K_s - 1; step k touches the band store in two
 parts, its rows rx .. rx+L-1 (part A: the reflector's column, the bulge
 block, the diagonal block) and its block below (part B), with rx, L and the
 block shapes as the kernel forms them.  One workgroup runs a sweep's parts in
-order; part A of step k of sweep s starts once sweep s-1 has finished
-min(k+2, K_{s-1}) steps, part B (when the step has a block below) once it has
-finished min(k+3, K_{s-1}).  These waits, with program order, define a
-partial order on all parts.  The sequential algorithm runs sweep after sweep,
+order and publishes step k (progress k+1) once its part A is done; part A of
+step k of sweep s starts once sweep s-1 has published min(k+2, K_{s-1}) steps,
+part B (when the step has a block below) once it has published
+min(k+3, K_{s-1}).  These waits, with program order, define a partial order
+on all parts.  The sequential algorithm runs sweep after sweep,
 so every element two sweeps touch must be touched by the earlier sweep's part
 first: the test checks that for every such pair the earlier part precedes the
 later one in the partial order (which also keeps valid the block a sweep
@@ -45,8 +46,9 @@ def step_parts(n, w, s, k):
     return A, B
 
 
-def check_schedule(n, w, lag_a=2, lag_b=3):
-    """Returns the list of element conflicts the waits fail to order."""
+def check_schedule(n, w, lag_a=2, lag_b=3, publish_after_a=True):
+    """Returns the list of element conflicts the waits fail to order
+    (publish_after_a=False: a step published only once both parts are done)."""
     S = max(0, n - 2)
     K = [sweep_steps(n, w, s) for s in range(S)]
     parts = {}
@@ -70,7 +72,8 @@ def check_schedule(n, w, lag_a=2, lag_b=3):
                     if has_wait:
                         need = min(k + lag, K[s - 1])
                         if need >= 1:
-                            src = 2 * (need - 1) + 1  # part B of step need-1
+                            # the event after which step need-1 is published
+                            src = 2 * (need - 1) + (0 if publish_after_a else 1)
                             cur[s - 1] = max(cur[s - 1], src)
                             # and everything that precedes that event
                             for q, idx in enumerate(before[s - 1][src]):
@@ -99,9 +102,10 @@ def test_stage2_waits_order_every_shared_element(n, w):
 
 
 @pytest.mark.parametrize("n,w", [(33, 4), (64, 8)])
-def test_stage2_earlier_three_step_lag_is_also_safe(n, w):
-    # the schedule before the split wait: every part 3 steps behind
-    assert not check_schedule(n, w, lag_a=3, lag_b=3)
+def test_stage2_earlier_schedules_are_also_safe(n, w):
+    # publication after the whole step, and every part 3 steps behind
+    assert not check_schedule(n, w, publish_after_a=False)
+    assert not check_schedule(n, w, lag_a=3, lag_b=3, publish_after_a=False)
 
 
 @pytest.mark.parametrize("n,w", [(17, 3), (33, 4), (64, 8)])
