@@ -279,9 +279,9 @@ __device__ __forceinline__ bool wait_prev(const Sb2stDesc &d, S2Lds &sh, int s, 
 // piece of a band-store column), updated there and written back.
 // kept: blk holds the block below of step k - 1 of this sweep as it was
 // written back (rows rx .., columns cx ..): this step's column and bulge
-// block, which no other sweep changes in between (the earlier sweep's steps
-// that meet them finished before step k - 1 began, the later ones start
-// below row rx + w)
+// block, which no other sweep changes in between (the earlier sweep's work on
+// it was published before step k - 1 loaded it, and the next sweep touches it
+// only after this step has published)
 // need_below: progress of sweep s-1 required before the block below is
 // loaded (0: none).
 // The step publishes itself (progress of sweep s = k + 1) as soon as its rows
